@@ -1,0 +1,138 @@
+/*
+ * abp.h -- C ABI of libabp, an MI355X (gfx950) library for ensembles of active Brownian particles
+ * with an energy depot on a periodic ratchet.
+ *
+ * Model (M. Zabicki, "OpenCL/OpenGL approach for studying active Brownian motion", Sec. 2):
+ *   Eq. (1)  de/dt = q - c e - d2 e v^2
+ *   Eq. (2)  dv/dt = F0 + d2 e v - gamma0 v - U'(x) + sqrt(2 D) xi(t),   dx/dt = v
+ *   Eq. (3)  U(x)  = U0 [ sin 2pi(x + phi) + a sin 4pi(x + phi) ]
+ * Each particle is one lane of a wavefront; its state stays in registers for the whole call, and
+ * its Gaussian noise is regenerated in registers from a counter-based generator instead of being
+ * read from memory (Sec. 2 prefers an on-device generator over host-filled random buffers).
+ *
+ * Noise contract. Philox4x32-10 (Salmon et al., SC'11) with key (seed mod 2^32, seed / 2^32) and
+ * counter (n / 4, particle id, set id, 0) for absolute step n; the four words of one block become
+ * four normals by Box-Muller (Fig. 1) on 24-bit uniforms u1 = ((w0 >> 8) + 1) 2^-24,
+ * u2 = (w1 >> 8) 2^-24: z0 = rho cos 2pi u2, z1 = rho sin 2pi u2, rho = sqrt(-2 ln u1), and
+ * likewise (w2, w3) -> z2, z3. Step n uses z[n mod 4]. Initial positions: x0 = (w0 >> 8) 2^-24 of
+ * block (0, particle id, set id, 1); v0 = e0 = 0.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are HIP device memory owned by the caller; h_* are host memory; structs
+ *    passed by pointer are host memory read during the call only. The library never frees or
+ *    keeps caller memory after returning, allocates no device memory, and never prints.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the null stream). The
+ *    status is returned synchronously: arguments are validated before anything is enqueued, and
+ *    on ABP_E_ARG / ABP_E_WORKSPACE / ABP_E_DEVICE nothing is written. ABP_E_HIP reports a
+ *    launch or copy error from the HIP runtime.
+ *  - Results are deterministic: identical inputs give bit-identical outputs for every tuning and
+ *    every repeat (FP64 partials are combined in a fixed order; histograms are integer counts).
+ *  - Only gfx950 devices are accepted (ABP_E_DEVICE otherwise).
+ */
+#ifndef ABP_H
+#define ABP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ABP_ABI_VERSION 1
+
+typedef enum abp_status {
+    ABP_OK = 0,
+    ABP_E_ARG = 1,       /* invalid argument (null/misaligned pointer, out-of-range value) */
+    ABP_E_HIP = 2,       /* HIP runtime error while enqueuing */
+    ABP_E_WORKSPACE = 3, /* workspace smaller than the matching *_workspace_bytes() query */
+    ABP_E_DEVICE = 4     /* current device is not gfx950 */
+} abp_status;
+
+typedef enum abp_scheme { ABP_EM = 0, ABP_HEUN = 1 } abp_scheme;
+
+/* Model parameters of Eqs. (1)-(3). D >= 0 (D = 0 is the deterministic limit). */
+typedef struct abp_params {
+    double U0, a, phi, gamma0, F0, d2, q, c, D;
+} abp_params;
+#define ABP_N_PARAMS 9 /* a device parameter table is an array of rows of these 9 doubles */
+
+/* One integration call. Step indices are absolute, so a run may be split into calls. */
+typedef struct abp_run {
+    double dt;          /* time step, > 0 */
+    int64_t n_steps;    /* steps taken by this call, >= 0 */
+    int64_t step0;      /* absolute index of the first step of this call, >= 0 */
+    int64_t win_begin;  /* absolute time index at which the averaging window opens: the position
+                           is copied into the snapshot before step win_begin is taken; -1 = none */
+    uint64_t seed;      /* Philox key */
+    uint32_t set_id;    /* Philox counter word 2 (parameter-set index) */
+    int32_t scheme;     /* abp_scheme */
+} abp_run;
+/* step0 + n_steps must not exceed 2^34 (the block counter n/4 is one 32-bit word). */
+
+/* Particle state in structure-of-arrays form, device memory, n entries each. The position is
+ * x = cell + xf with an integer cell and an FP32 fraction xf (kept near [0, 1)), so FP32 never
+ * adds a small increment to a large coordinate. Particle i has Philox id id0 + i. */
+typedef struct abp_state {
+    int32_t *d_cell;
+    float *d_xf;
+    float *d_v;
+    float *d_e;
+    int64_t n;     /* >= 1, <= 2^31 */
+    uint32_t id0;  /* id of particle 0; id0 + n - 1 must fit in 32 bits */
+    uint32_t pad;
+} abp_state;
+
+/* Launch shape. Zero fields select the built-in default. block: threads per workgroup (64, 128
+ * or 256); ppl: particles per lane (1 or 2); unroll: Philox blocks (4 steps each) per loop
+ * iteration (1 or 2); waves_per_simd: residency target of the persistent batched launch (1-8). */
+typedef struct abp_tuning {
+    int32_t block, ppl, unroll, waves_per_simd;
+} abp_tuning;
+
+int abp_abi_version(void);
+const char *abp_status_str(abp_status s);
+
+/* Initial condition x0 ~ U[0,1) (24-bit grid), v0 = e0 = 0, of particles id0..id0+n-1 of set
+ * `set_id` under `seed` (see the noise contract). */
+abp_status abp_init_state(const abp_state *s, uint64_t seed, uint32_t set_id, void *stream);
+
+/* Philox4x32-10 of m counters: d_ctr [m][4] u32, d_key [m][2] u32 -> d_out [m][4] u32. The
+ * generator the integrators use, exposed so that it can be checked bit for bit. */
+abp_status abp_philox(int64_t m, const uint32_t *d_ctr, const uint32_t *d_key, uint32_t *d_out,
+                      void *stream);
+
+/* Bytes of the reduction workspace for n particles and n_bins histogram bins (0 or a power of
+ * two up to 4096): FP64 partial sums per 64-particle tile plus a u32 histogram. */
+size_t abp_reduce_workspace_bytes(int64_t n, int32_t n_bins);
+
+/* Advance the ensemble by r->n_steps steps of the chosen scheme (Eqs. (1)-(3); the per-step loop
+ * of Fig. 1), in place on *s. Euler-Maruyama evaluates all drifts at the old state; Heun averages
+ * the drifts at the old state and at the Euler predictor, with the same normal.
+ *  snap: where the window snapshot (cell, xf) is written when step0 <= win_begin <= step0+n_steps
+ *        and read from when win_begin < step0; may be NULL if win_begin < 0. v and e unused.
+ *  d_ws: if non-NULL, the call also reduces the ensemble at its end: per-tile FP64 sums of the
+ *        window displacement and its square, and the histogram of x mod 1 (n_bins bins), are
+ *        written to d_ws (ws_bytes >= abp_reduce_workspace_bytes(n, n_bins)); abp_reduce turns
+ *        them into results. Requires a window (win_begin >= 0, win_begin <= step0 + n_steps).
+ *  tune: NULL = default launch shape. */
+abp_status abp_integrate(const abp_params *p, const abp_run *r, const abp_state *s,
+                         const abp_state *snap, void *d_ws, size_t ws_bytes, int32_t n_bins,
+                         const abp_tuning *tune, void *stream);
+
+/* Finish a reduction left in d_ws by abp_integrate or abp_reduce_state for n particles:
+ * d_out[0] = mean drift velocity = sum(delta) / (n window_time), d_out[1] = its standard error,
+ * d_hist[n_bins] = u64 counts of particles with floor(n_bins (x - floor x)) = b (clamped to
+ * n_bins - 1), x = cell + xf evaluated in FP64. d_hist may be NULL when n_bins = 0. */
+abp_status abp_reduce(const void *d_ws, int64_t n, int32_t n_bins, double window_time,
+                      double *d_out, uint64_t *d_hist, void *stream);
+
+/* The reduction stage alone, from two states (window start and end): writes the same partials
+ * into d_ws as abp_integrate does. */
+abp_status abp_reduce_state(const abp_state *snap, const abp_state *end, int32_t n_bins,
+                            void *d_ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABP_H */

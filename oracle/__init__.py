@@ -63,7 +63,7 @@ def _load():
     lib.orc_potential.argtypes = [P(_Params), f64]
     lib.orc_potential.restype = f64
     lib.orc_integrate.argtypes = [P(_Params), ctypes.c_int, f64, i64, i64, i64, u64, u32, i64, vp,
-                                  vp, vp, vp, vp, vp]
+                                  vp, vp, vp, vp, vp, f64]
     lib.orc_integrate.restype = ctypes.c_int
     lib.orc_reduce.argtypes = [i64, vp, vp, f64, i32, vp, vp]
     lib.orc_rk4.argtypes = [P(_Params), f64, i64, i64, vp, vp, vp]
@@ -137,12 +137,13 @@ def potential(params: dict | None, x: float) -> float:
 
 def integrate(params: dict | None, x, v, e, n_steps: int, dt: float = 1e-3, scheme: int = EM,
               seed: int = 42, set_id: int = 0, step0: int = 0, win_begin: int = -1, ids=None,
-              x_snap=None, v_sum=None):
+              x_snap=None, v_sum=None, eps: float = 0.0):
     """Advance copies of (x, v, e) by n_steps from absolute step step0.
 
     Returns (x, v, e, x_snap, v_sum). ``x_snap`` holds x at absolute index ``win_begin`` when the
     window opens inside [step0, step0 + n_steps] and is carried in from ``x_snap`` otherwise;
-    ``v_sum`` accumulates v_n over window steps (time-average estimator)."""
+    ``v_sum`` accumulates v_n over window steps (time-average estimator). ``eps`` != 0 applies
+    the rounding-sensitivity model after each step (x += eps u, v and e scaled by 1 + eps u)."""
     x = np.array(x, dtype=np.float64, copy=True)
     v = np.array(v, dtype=np.float64, copy=True)
     e = np.array(e, dtype=np.float64, copy=True)
@@ -152,7 +153,8 @@ def integrate(params: dict | None, x, v, e, n_steps: int, dt: float = 1e-3, sche
     ids = _ids(ids, n)
     p = _params(params)
     rc = _load().orc_integrate(ctypes.byref(p), scheme, dt, step0, n_steps, win_begin, seed,
-                               set_id, n, _ptr(ids), _ptr(x), _ptr(v), _ptr(e), _ptr(xs), _ptr(vs))
+                               set_id, n, _ptr(ids), _ptr(x), _ptr(v), _ptr(e), _ptr(xs), _ptr(vs),
+                               float(eps))
     if rc != 0:
         raise ValueError("oracle integrate rejected its arguments")
     return x, v, e, xs, vs

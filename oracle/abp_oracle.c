@@ -170,13 +170,30 @@ static void one_step(const orc_params *p, int scheme, double dt, double sig, dou
     y[2] = y[2] + 0.5 * (f[2] + g[2]) * dt;
 }
 
+/* Sensitivity model of single-precision state rounding (not part of the method): after each step
+ * x moves by eps*u0 (absolute: a position fraction in [0,1) carries absolute rounding), and v, e
+ * are scaled by (1 + eps*u1), (1 + eps*u2), with u uniform on [-1,1) from Philox domain 3. With
+ * eps = 2^-24 it measures how far the dynamics itself amplifies FP32-sized rounding. */
+static void perturb(uint64_t seed, uint32_t pid, uint32_t set, int64_t step, double eps, double y[3])
+{
+    uint32_t r[4];
+    philox_for(seed, (uint32_t)step, pid, set, 3u, r);
+    double u[3];
+    for (int j = 0; j < 3; ++j)
+        u[j] = (double)(r[j] >> 8) * 0x1p-23 - 1.0;
+    y[0] += eps * u[0];
+    y[1] *= 1.0 + eps * u[1];
+    y[2] *= 1.0 + eps * u[2];
+}
+
 /* Advance n particles from absolute step step0 by n_steps steps (Fig. 1's loop).
  * x_snap[i] receives x at absolute time index win_begin when step0 <= win_begin <= step0+n_steps
  * (i.e. before step win_begin is taken); v_sum[i] (optional) accumulates v_n over the steps with
- * n >= win_begin, the time-average estimator of the mean velocity. Returns 0, or -1 on bad input. */
+ * n >= win_begin, the time-average estimator of the mean velocity. eps != 0 applies the rounding
+ * sensitivity model after every step. Returns 0, or -1 on bad input. */
 int orc_integrate(const orc_params *p, int scheme, double dt, int64_t step0, int64_t n_steps,
                   int64_t win_begin, uint64_t seed, uint32_t set, int64_t n, const uint32_t *ids,
-                  double *x, double *v, double *e, double *x_snap, double *v_sum)
+                  double *x, double *v, double *e, double *x_snap, double *v_sum, double eps)
 {
     if (!(dt > 0.0) || n_steps < 0 || step0 < 0 || n < 0 || p->D < 0.0)
         return -1;
@@ -198,6 +215,8 @@ int orc_integrate(const orc_params *p, int scheme, double dt, int64_t step0, int
             if (win_begin >= 0 && step >= win_begin)
                 vs += y[1];
             one_step(p, scheme, dt, sig, z[step % 4], y);
+            if (eps != 0.0)
+                perturb(seed, pid, set, step, eps, y);
         }
         if (win_begin == step0 + n_steps && x_snap)
             x_snap[i] = y[0];

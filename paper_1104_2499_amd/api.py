@@ -1,0 +1,193 @@
+"""Python front end of libabp: torch tensors for device memory and streams, ctypes for the calls.
+
+Every numerical step runs in the HIP library; this module only allocates buffers, fills the ABI
+structs and checks status codes.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from .workloads import BASE_PARAMS, PARAM_KEYS
+
+SCHEMES = {"em": _lib.ABP_EM, "heun": _lib.ABP_HEUN}
+
+
+class AbpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = _lib.load()
+        msg = lib.abp_status_str(status).decode()
+        super().__init__(f"{where}: {_lib.STATUS_NAMES.get(status, status)} ({msg})")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != _lib.ABP_OK:
+        raise AbpError(status, where)
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p | None:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def scheme_id(scheme) -> int:
+    if isinstance(scheme, str):
+        return SCHEMES[scheme.lower()]
+    return int(scheme)
+
+
+def make_params(params: dict | None = None) -> _lib.AbpParams:
+    d = dict(BASE_PARAMS)
+    if params:
+        unknown = set(params) - set(PARAM_KEYS)
+        if unknown:
+            raise KeyError(f"unknown parameter(s) {sorted(unknown)}")
+        d.update(params)
+    return _lib.AbpParams(*[float(d[k]) for k in PARAM_KEYS])
+
+
+def make_tuning(tune) -> _lib.AbpTuning | None:
+    if tune is None:
+        return None
+    if isinstance(tune, _lib.AbpTuning):
+        return tune
+    t = dict(tune)
+    return _lib.AbpTuning(int(t.get("block", 0)), int(t.get("ppl", 0)), int(t.get("unroll", 0)),
+                          int(t.get("waves_per_simd", 0)))
+
+
+@dataclass
+class State:
+    """Structure-of-arrays particle state on the device: x = cell + xf."""
+    cell: torch.Tensor
+    xf: torch.Tensor
+    v: torch.Tensor
+    e: torch.Tensor
+    id0: int = 0
+
+    @property
+    def n(self) -> int:
+        return self.cell.numel()
+
+    @staticmethod
+    def empty(n: int, device="cuda", id0: int = 0) -> "State":
+        return State(torch.empty(n, dtype=torch.int32, device=device),
+                     torch.empty(n, dtype=torch.float32, device=device),
+                     torch.empty(n, dtype=torch.float32, device=device),
+                     torch.empty(n, dtype=torch.float32, device=device), id0)
+
+    def clone(self) -> "State":
+        return State(self.cell.clone(), self.xf.clone(), self.v.clone(), self.e.clone(), self.id0)
+
+    def abi(self) -> _lib.AbpState:
+        for t, dt in ((self.cell, torch.int32), (self.xf, torch.float32), (self.v, torch.float32),
+                      (self.e, torch.float32)):
+            if t.dtype != dt or not t.is_contiguous() or t.numel() != self.n:
+                raise ValueError("state tensors must be contiguous int32/float32 of equal length")
+        return _lib.AbpState(self.cell.data_ptr(), self.xf.data_ptr(), self.v.data_ptr(),
+                             self.e.data_ptr(), self.n, self.id0, 0)
+
+    def x64(self) -> torch.Tensor:
+        """Positions cell + xf in float64 (on the state's device)."""
+        return self.cell.double() + self.xf.double()
+
+
+def reset_state(s: State, seed: int, set_id: int = 0, stream=None) -> State:
+    """Write the workload initial condition (x0 ~ U[0,1) from Philox, v0 = e0 = 0) into `s`."""
+    abi = s.abi()
+    check(_lib.load().abp_init_state(ctypes.byref(abi), seed, set_id, _stream(stream)),
+          "abp_init_state")
+    return s
+
+
+def init_state(n: int, seed: int, set_id: int = 0, id0: int = 0, device="cuda",
+               stream=None) -> State:
+    return reset_state(State.empty(n, device, id0), seed, set_id, stream)
+
+
+def philox(ctr: torch.Tensor, key: torch.Tensor, stream=None) -> torch.Tensor:
+    """Philox4x32-10 on the device; ctr [m,4] and key [m,2] int32 tensors holding u32 bits."""
+    if ctr.dtype != torch.int32 or key.dtype != torch.int32:
+        raise TypeError("ctr and key must be int32 tensors (u32 bit patterns)")
+    ctr = ctr.contiguous()
+    key = key.contiguous()
+    m = ctr.shape[0]
+    out = torch.empty((m, 4), dtype=torch.int32, device=ctr.device)
+    check(_lib.load().abp_philox(m, _ptr(ctr), _ptr(key), _ptr(out), _stream(stream)),
+          "abp_philox")
+    return out
+
+
+def reduce_workspace(n: int, n_bins: int, device="cuda") -> torch.Tensor:
+    nbytes = int(_lib.load().abp_reduce_workspace_bytes(n, n_bins))
+    if nbytes == 0:
+        raise ValueError("invalid reduction size")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def integrate(state: State, n_steps: int, params: dict | None = None, dt: float = 1e-3,
+              scheme="em", seed: int = 42, set_id: int = 0, step0: int = 0, win_begin: int = -1,
+              snap: State | None = None, ws: torch.Tensor | None = None, n_bins: int = 0,
+              tune=None, stream=None) -> None:
+    """Advance `state` in place (abp_integrate). With `ws`, also leave the reduction partials."""
+    p = make_params(params)
+    r = _lib.AbpRun(dt, n_steps, step0, win_begin, seed, set_id, scheme_id(scheme))
+    s = state.abi()
+    sn = snap.abi() if snap is not None else None
+    t = make_tuning(tune)
+    check(_lib.load().abp_integrate(ctypes.byref(p), ctypes.byref(r), ctypes.byref(s),
+                                    ctypes.byref(sn) if sn is not None else None, _ptr(ws),
+                                    0 if ws is None else ws.numel(), n_bins,
+                                    ctypes.byref(t) if t is not None else None, _stream(stream)),
+          "abp_integrate")
+
+
+def reduce(ws: torch.Tensor, n: int, n_bins: int, window_time: float, stream=None):
+    """(mean velocity, standard error) as a float64 [2] tensor and the uint64 histogram."""
+    out = torch.empty(2, dtype=torch.float64, device=ws.device)
+    hist = torch.empty(max(n_bins, 1), dtype=torch.int64, device=ws.device)
+    check(_lib.load().abp_reduce(_ptr(ws), n, n_bins, window_time, _ptr(out),
+                                 _ptr(hist) if n_bins > 0 else None, _stream(stream)),
+          "abp_reduce")
+    return out, hist[:n_bins]
+
+
+def reduce_state(snap: State, end: State, n_bins: int, ws: torch.Tensor, stream=None) -> None:
+    a, b = snap.abi(), end.abi()
+    check(_lib.load().abp_reduce_state(ctypes.byref(a), ctypes.byref(b), n_bins, _ptr(ws),
+                                       ws.numel(), _stream(stream)), "abp_reduce_state")
+
+
+@dataclass
+class Result:
+    mean_v: float
+    stderr: float
+    hist: torch.Tensor
+    state: State
+    snap: State
+
+
+def run(params: dict | None = None, n: int = 1024, steps: int = 10_000, window: int | None = None,
+        dt: float = 1e-3, scheme="em", seed: int = 42, bins: int = 256, set_id: int = 0,
+        tune=None, device="cuda", stream=None) -> Result:
+    """Initial condition, `steps` steps, window mean velocity over the last `window` steps
+    (default: the last half) and the histogram of the final x mod 1."""
+    window = steps // 2 if window is None else window
+    if not 1 <= window <= steps:
+        raise ValueError("need 1 <= window <= steps")
+    st = init_state(n, seed, set_id, device=device, stream=stream)
+    snap = State.empty(n, device)
+    ws = reduce_workspace(n, bins, device)
+    integrate(st, steps, params, dt, scheme, seed, set_id, 0, steps - window, snap, ws, bins,
+              tune, stream)
+    out, hist = reduce(ws, n, bins, window * dt, stream)
+    o = out.cpu()
+    return Result(float(o[0]), float(o[1]), hist, st, snap)

@@ -1,0 +1,263 @@
+// device.hpp -- per-lane building blocks of the ABP integrator on gfx950.
+//
+// One particle (or two, PPL = 2) per lane; the state (cell, xf, v, e) lives in VGPRs for the whole
+// launch. Everything uniform across a wavefront (model constants, Philox key schedule, step
+// indices) is computed from kernel arguments and stays in SGPRs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace abp {
+
+// ---------------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds; each multiplies words 0 and 2 by
+// the round constants, returning the high halves xor-ed with the neighbouring word and the key,
+// and the low halves as the new words 1 and 3; the key is bumped by the Weyl increments between
+// rounds. Words whose inputs are wavefront-uniform (the step block, set id and domain) stay on
+// the scalar unit for the first rounds; the rest is v_mad_u64_u32 + v_bitop3_b32 per word pair.
+// ---------------------------------------------------------------------------------------------
+struct Philox4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0, n2;
+        if (r < 3) {
+            // counter words still partly wavefront-uniform: let the scalar unit take its share
+            n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        } else {
+            // three-input xor in one VALU op (gfx950 v_bitop3_b32, truth table 0x96)
+            n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), c1, k0, 0x96);
+            n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), c3, k1, 0x96);
+        }
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Philox4 o;
+    o.w[0] = c0;
+    o.w[1] = c1;
+    o.w[2] = c2;
+    o.w[3] = c3;
+    return o;
+}
+
+enum : uint32_t { kDomainNoise = 0u, kDomainInit = 1u };
+
+// ---------------------------------------------------------------------------------------------
+// Box-Muller on 24-bit uniforms, with the noise amplitude folded in: returns sigma*z0, sigma*z1.
+// u1 = (m+1) 2^-24 in (0, 1] and u2 = m' 2^-24 in [0, 1) are exact in FP32. The hardware
+// transcendentals are used directly: v_log_f32 is log2, and v_sin_f32 / v_cos_f32 take their
+// argument in revolutions, so sin(2 pi u2) is v_sin_f32(u2) with no range reduction.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void box_muller_scaled(uint32_t wa, uint32_t wb, float sigma,
+                                                  float &za, float &zb)
+{
+    const float u1 = (float)((wa >> 8) + 1u) * 0x1p-24f;
+    const float u2 = (float)(wb >> 8) * 0x1p-24f;
+    const float minus_2ln2 = -1.38629436111989061883f;
+    const float rho = __builtin_amdgcn_sqrtf(minus_2ln2 * __builtin_amdgcn_logf(u1));
+    const float s = sigma * rho;
+    za = s * __builtin_amdgcn_cosf(u2);
+    zb = s * __builtin_amdgcn_sinf(u2);
+}
+
+// Noise block b of particle `pid`: sigma * (z0, z1, z2, z3) for steps 4b .. 4b+3.
+struct Noise4 {
+    float z[4];
+};
+
+__device__ __forceinline__ Noise4 noise_block(uint32_t blk, uint32_t pid, uint32_t set,
+                                              uint32_t k0, uint32_t k1, float sigma)
+{
+    const Philox4 r = philox4x32_10(blk, pid, set, kDomainNoise, k0, k1);
+    Noise4 n;
+    box_muller_scaled(r.w[0], r.w[1], sigma, n.z[0], n.z[1]);
+    box_muller_scaled(r.w[2], r.w[3], sigma, n.z[2], n.z[3]);
+    return n;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Drift of Eqs. (1)-(3) in FP32, wavefront-uniform coefficients.
+//   U'(x) = 2 pi U0 [cos th + 2a cos 2th], th = 2 pi (x + phi); with c = cos th and the double
+//   angle cos 2th = 2c^2 - 1:  F0 - U'(x) = (F0 + 4 pi U0 a) - c (2 pi U0 + 8 pi U0 a c).
+//   f_v = F0 - U'(x) + (d2 e - gamma0) v,   f_e = q - e (c + d2 v^2).
+// ---------------------------------------------------------------------------------------------
+struct Coef {
+    float dt, half_dt, sigma, phi;
+    float K1;   // 2 pi U0
+    float B;    // 8 pi U0 a
+    float FH;   // F0 + 4 pi U0 a
+    float g0, d2, q, c;
+};
+
+__device__ __forceinline__ void drift(const Coef &k, float xf, float v, float e, float &fv,
+                                      float &fe)
+{
+    const float cth = __builtin_amdgcn_cosf(xf + k.phi);
+    const float fu = fmaf(-cth, fmaf(k.B, cth, k.K1), k.FH);
+    fv = fmaf(fmaf(k.d2, e, -k.g0), v, fu);
+    fe = fmaf(-e, fmaf(k.d2 * v, v, k.c), k.q);
+}
+
+struct Particle {
+    int32_t cell;
+    float xf, v, e;
+};
+
+// Euler-Maruyama: every drift at the old state; zs = sigma * xi_n.
+__device__ __forceinline__ void step_em(const Coef &k, Particle &p, float zs)
+{
+    float fv, fe;
+    drift(k, p.xf, p.v, p.e, fv, fe);
+    p.xf = fmaf(p.v, k.dt, p.xf);
+    p.v = p.v + fmaf(fv, k.dt, zs);
+    p.e = fmaf(fe, k.dt, p.e);
+}
+
+// Stochastic Heun for additive noise: Euler predictor with the same normal, then the
+// trapezoidal average of the two drifts.
+__device__ __forceinline__ void step_heun(const Coef &k, Particle &p, float zs)
+{
+    float fv0, fe0, fv1, fe1;
+    drift(k, p.xf, p.v, p.e, fv0, fe0);
+    const float xp = fmaf(p.v, k.dt, p.xf);
+    const float vp = p.v + fmaf(fv0, k.dt, zs);
+    const float ep = fmaf(fe0, k.dt, p.e);
+    drift(k, xp, vp, ep, fv1, fe1);
+    p.xf = fmaf(p.v + vp, k.half_dt, p.xf);
+    p.v = p.v + fmaf(fv0 + fv1, k.half_dt, zs);
+    p.e = fmaf(fe0 + fe1, k.half_dt, p.e);
+}
+
+template <int SCHEME>
+__device__ __forceinline__ void step(const Coef &k, Particle &p, float zs)
+{
+    if constexpr (SCHEME == 0)
+        step_em(k, p, zs);
+    else
+        step_heun(k, p, zs);
+}
+
+// Periodic bookkeeping after every aligned block of four steps: move the integer part of xf into
+// the cell. xf only leaves [0, 1) by |v| dt per step, and cos is periodic, so doing this once per
+// block keeps FP32 resolution while costing about one instruction per step.
+__device__ __forceinline__ void wrap(Particle &p)
+{
+    const float fl = floorf(p.xf);
+    p.xf -= fl;
+    p.cell += (int32_t)fl;
+}
+
+__device__ __forceinline__ float pick(const Noise4 &n, uint32_t j)
+{
+    return j == 0 ? n.z[0] : j == 1 ? n.z[1] : j == 2 ? n.z[2] : n.z[3];
+}
+
+// Wavefront-uniform description of one particle set's noise and steps.
+struct Stream {
+    uint32_t k0, k1;  // Philox key
+    uint32_t set;
+};
+
+// Advance PPL particles of one lane from absolute step n to `stop` (both wavefront-uniform).
+// Blocks of four steps aligned on absolute indices take the fast path; a call that starts or
+// ends inside a block handles its partial block step by step. Wraps happen only after absolute
+// steps 4b+3, so any split of a run into calls gives bit-identical states.
+template <int SCHEME, int PPL, int UNROLL>
+__device__ __forceinline__ void advance(const Coef &k, const Stream &s, const uint32_t (&pid)[PPL],
+                                        Particle (&p)[PPL], int64_t &n, int64_t stop)
+{
+    // leading partial block
+    if (n < stop && (n & 3)) {
+        const uint32_t blk = (uint32_t)(n >> 2);
+        const uint32_t j0 = (uint32_t)(n & 3);
+        const uint32_t j1 = (uint32_t)((stop - n) < (int64_t)(4 - j0) ? j0 + (stop - n) : 4);
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.sigma);
+            for (uint32_t j = j0; j < j1; ++j)
+                step<SCHEME>(k, p[q], pick(z, j));
+            if (j1 == 4)
+                wrap(p[q]);
+        }
+        n += (int64_t)(j1 - j0);
+    }
+    // aligned blocks
+    const int64_t nblk = (stop - n) >> 2;
+    uint32_t blk = (uint32_t)(n >> 2);
+    int64_t b = 0;
+    for (; b + UNROLL <= nblk; b += UNROLL) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                const Noise4 z = noise_block(blk + u, pid[q], s.set, s.k0, s.k1, k.sigma);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    step<SCHEME>(k, p[q], z.z[j]);
+                wrap(p[q]);
+            }
+        }
+        blk += UNROLL;
+    }
+    for (; b < nblk; ++b) {
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.sigma);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                step<SCHEME>(k, p[q], z.z[j]);
+            wrap(p[q]);
+        }
+        ++blk;
+    }
+    n += nblk << 2;
+    // trailing partial block (no wrap: the block is finished by the next call)
+    if (n < stop) {
+        const uint32_t j1 = (uint32_t)(stop - n);
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.sigma);
+            for (uint32_t j = 0; j < j1; ++j)
+                step<SCHEME>(k, p[q], pick(z, j));
+        }
+        n = stop;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Reduction helpers
+// ---------------------------------------------------------------------------------------------
+// Butterfly sum over the 64 lanes of a wavefront in a fixed order (every lane ends with the total).
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+// Histogram bin of x = cell + xf, decided in FP64: floor(n_bins * (x - floor x)), clamped.
+__device__ __forceinline__ int32_t hist_bin(int32_t cell, float xf, int32_t n_bins)
+{
+    const double x = (double)cell + (double)xf;
+    const double frac = x - floor(x);
+    if (!(frac >= 0.0))
+        return 0;  // not reached for finite positions
+    const int32_t b = (int32_t)floor(frac * (double)n_bins);
+    return b >= n_bins ? n_bins - 1 : b;
+}
+
+}  // namespace abp

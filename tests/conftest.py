@@ -19,3 +19,25 @@ def orc():
 
     oracle._load()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """The HIP library on cuda:0. GPU tests fail (never skip) if the device or library is absent."""
+    import torch
+
+    assert torch.cuda.is_available(), "gpu-marked test needs a HIP device"
+    from paper_1104_2499_amd import _lib
+
+    lib = _lib.load()
+    assert lib.abp_abi_version() == 1
+    return lib
+
+
+def mixed_err(gpu_xyz, ora_xyz):
+    """Per-trajectory max over (x, v, e) of |gpu - oracle| / max(1, |oracle|)."""
+    import numpy as np
+
+    errs = [np.abs(np.asarray(g, np.float64) - o) / np.maximum(1.0, np.abs(o))
+            for g, o in zip(gpu_xyz, ora_xyz)]
+    return np.max(np.stack(errs), axis=0)

@@ -1,0 +1,136 @@
+"""CPU checks of the C ABI: the library builds, loads, exports every declared entry point, and
+rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "abp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(abp_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1104_2499_amd import _lib, build
+
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported_and_bound(lib):
+    from paper_1104_2499_amd import _lib
+
+    names = declared_functions()
+    assert len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"{name} has no Python binding"
+
+
+def test_version_and_status_strings(lib):
+    assert lib.abp_abi_version() == 1
+    for s in range(5):
+        assert lib.abp_status_str(s)
+    assert lib.abp_status_str(99) == b"unknown status"
+
+
+def test_workspace_queries(lib):
+    assert lib.abp_reduce_workspace_bytes(0, 256) == 0
+    assert lib.abp_reduce_workspace_bytes(100, 3) == 0
+    assert lib.abp_reduce_workspace_bytes(100, 8192) == 0
+    a = lib.abp_reduce_workspace_bytes(1 << 20, 256)
+    assert a >= (1 << 14) * 16 + 256 * 4
+    assert lib.abp_reduce_workspace_bytes(64, 0) >= 16
+
+
+def _state(n=64, ptr=0x1000, id0=0):
+    from paper_1104_2499_amd import _lib
+
+    return _lib.AbpState(ptr, ptr, ptr, ptr, n, id0, 0)
+
+
+def test_integrate_rejects_bad_arguments_without_a_device(lib):
+    from paper_1104_2499_amd import _lib
+    from paper_1104_2499_amd.api import make_params
+
+    p = make_params()
+    good = _lib.AbpRun(1e-3, 100, 0, -1, 42, 0, 0)
+    s = _state()
+    E_ARG = _lib.ABP_E_ARG
+
+    def call(p_=p, r=good, s_=s, snap=None, ws=None, wsb=0, bins=0, tune=None):
+        return lib.abp_integrate(ctypes.byref(p_) if p_ is not None else None,
+                                 ctypes.byref(r) if r is not None else None,
+                                 ctypes.byref(s_) if s_ is not None else None,
+                                 ctypes.byref(snap) if snap is not None else None,
+                                 ws, wsb, bins, ctypes.byref(tune) if tune else None, None)
+
+    assert call(p_=None) == E_ARG
+    assert call(r=None) == E_ARG
+    assert call(s_=None) == E_ARG
+    for bad in (_lib.AbpRun(0.0, 100, 0, -1, 42, 0, 0), _lib.AbpRun(-1e-3, 100, 0, -1, 42, 0, 0),
+                _lib.AbpRun(float("nan"), 100, 0, -1, 42, 0, 0),
+                _lib.AbpRun(1e-3, -1, 0, -1, 42, 0, 0), _lib.AbpRun(1e-3, 100, -4, -1, 42, 0, 0),
+                _lib.AbpRun(1e-3, 1 << 34, 1, -1, 42, 0, 0),
+                _lib.AbpRun(1e-3, 100, 0, -2, 42, 0, 0), _lib.AbpRun(1e-3, 100, 0, -1, 42, 0, 7)):
+        assert call(r=bad) == E_ARG
+    assert call(s_=_state(n=0)) == E_ARG
+    assert call(s_=_state(ptr=0x1002)) == E_ARG            # misaligned
+    assert call(s_=_state(n=10, id0=0xFFFFFFFF)) == E_ARG   # ids overflow 32 bits
+    bad_p = make_params(dict(D=-0.1))
+    assert call(p_=bad_p) == E_ARG
+    assert call(p_=make_params(dict(U0=float("inf")))) == E_ARG
+    # window inside the call but no snapshot buffer
+    assert call(r=_lib.AbpRun(1e-3, 100, 0, 50, 42, 0, 0)) == E_ARG
+    # reduction without a window, or with bad bins / small workspace
+    ws = 0x10000
+    assert call(ws=ws, wsb=1 << 20, bins=256, snap=_state()) == E_ARG
+    win = _lib.AbpRun(1e-3, 100, 0, 50, 42, 0, 0)
+    assert call(r=win, ws=ws, wsb=1 << 20, bins=100, snap=_state()) == E_ARG
+    assert call(r=win, ws=ws, wsb=16, bins=256, snap=_state()) == _lib.ABP_E_WORKSPACE
+    assert call(tune=_lib.AbpTuning(96, 1, 1, 0)) == E_ARG
+    assert call(tune=_lib.AbpTuning(256, 3, 1, 0)) == E_ARG
+    assert call(tune=_lib.AbpTuning(256, 1, 4, 0)) == E_ARG
+
+
+def test_valid_call_without_gpu_reports_device(lib):
+    """On this host there is no gfx950 device: a valid call must say so, not crash or compute."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    from paper_1104_2499_amd import _lib
+    from paper_1104_2499_amd.api import make_params
+
+    p = make_params()
+    r = _lib.AbpRun(1e-3, 100, 0, -1, 42, 0, 0)
+    s = _state()
+    st = lib.abp_integrate(ctypes.byref(p), ctypes.byref(r), ctypes.byref(s), None, None, 0, 0,
+                           None, None)
+    assert st == _lib.ABP_E_DEVICE
+
+
+def test_other_entry_points_validate(lib):
+    from paper_1104_2499_amd import _lib
+
+    E_ARG = _lib.ABP_E_ARG
+    assert lib.abp_philox(0, 0x1000, 0x1000, 0x1000, None) == E_ARG
+    assert lib.abp_philox(4, None, 0x1000, 0x1000, None) == E_ARG
+    assert lib.abp_init_state(None, 1, 0, None) == E_ARG
+    assert lib.abp_reduce(None, 10, 256, 1.0, 0x1000, 0x1000, None) == E_ARG
+    assert lib.abp_reduce(0x10000, 10, 256, 0.0, 0x1000, 0x1000, None) == E_ARG
+    assert lib.abp_reduce(0x10000, 10, 256, 1.0, 0x1000, None, None) == E_ARG
+    a, b = _state(), _state(n=32)
+    assert lib.abp_reduce_state(ctypes.byref(a), ctypes.byref(b), 256, 0x10000, 1 << 20,
+                                None) == E_ARG
+    b = _state()
+    assert lib.abp_reduce_state(ctypes.byref(a), ctypes.byref(b), 256, 0x10000, 8,
+                                None) == _lib.ABP_E_WORKSPACE

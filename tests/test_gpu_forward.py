@@ -1,0 +1,273 @@
+"""GPU parity of the forward integrator and its reductions against the FP64 oracle.
+
+Readings used for the tolerances (the dynamics amplify any rounding; see the design notes):
+* per trajectory, 1e3 steps: >= 99.9% within 1e-4 and all within 1e-3 (mixed error, max over
+  x, v, e of |gpu - oracle| / max(1, |oracle|));
+* per trajectory, 1e4 steps: median within 1e-4, and the p50 / p90 / p99 of the GPU-oracle error
+  at most twice the oracle's own divergence under FP32-sized perturbations (plus a floor);
+* ensemble mean velocity: 1e-5 absolute;
+* histograms: bit-exact on identical states; otherwise they differ only by particles whose
+  trajectories differ.
+"""
+import numpy as np
+import pytest
+import torch
+
+from conftest import mixed_err
+
+pytestmark = pytest.mark.gpu
+
+BASE = dict(U0=1.0, a=0.25, phi=0.0, gamma0=1.0, F0=0.0, d2=1.0, q=1.0, c=0.1, D=0.1)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _u32_as_i32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32))
+
+
+def test_philox_bit_exact(gpu, orc):
+    from paper_1104_2499_amd import api
+
+    rng = np.random.default_rng(7)
+    m = 1 << 20
+    ctr = rng.integers(0, 2**32, size=(m, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(m, 2), dtype=np.uint64).astype(np.uint32)
+    key[:4] = [[0, 0], [0xFFFFFFFF, 0xFFFFFFFF], [0, 0xFFFFFFFF], [0xFFFFFFFF, 0]]
+    ctr[:4] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4, [0xFFFFFFFF, 0, 0, 0], [0, 0, 0, 0xFFFFFFFF]]
+    out = api.philox(_u32_as_i32(ctr).cuda(), _u32_as_i32(key).cuda())
+    got = _np(out).view(np.uint32)
+    np.testing.assert_array_equal(got, orc.philox(ctr, key))
+
+
+@pytest.mark.parametrize("n,id0,seed,set_id", [(5000, 0, 42, 0), (77, 123456, 2**40 + 5, 9),
+                                                (1, 0xFFFFFFFF, 0, 0)])
+def test_init_state_bit_exact(gpu, orc, n, id0, seed, set_id):
+    from paper_1104_2499_amd import api
+
+    s = api.init_state(n, seed, set_id, id0=id0)
+    x, v, e = orc.init_state(n, seed, set_id, ids=np.arange(id0, id0 + n, dtype=np.uint64))
+    np.testing.assert_array_equal(_np(s.cell), 0)
+    np.testing.assert_array_equal(_np(s.xf).astype(np.float64), x)
+    assert not _np(s.v).any() and not _np(s.e).any()
+
+
+def _run_pair(orc, params, n, steps, scheme, seed=42, window=None, dt=1e-3, bins=256, tune=None,
+              set_id=0):
+    from paper_1104_2499_amd import api
+
+    window = steps // 2 if window is None else window
+    res = api.run(params, n=n, steps=steps, window=window, dt=dt, scheme=scheme, seed=seed,
+                  bins=bins, tune=tune, set_id=set_id)
+    x0, v0, e0 = orc.init_state(n, seed, set_id)
+    sid = 0 if scheme == "em" else 1
+    x, v, e, xs, _ = orc.integrate(params, x0, v0, e0, steps, dt=dt, scheme=sid, seed=seed,
+                                   set_id=set_id, win_begin=steps - window)
+    mean, se, hist = orc.reduce(xs, x, window * dt, bins)
+    return res, (x, v, e, xs), (mean, se, hist)
+
+
+def _gpu_xve(res):
+    return (_np(res.state.x64()), _np(res.state.v).astype(np.float64),
+            _np(res.state.e).astype(np.float64))
+
+
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_trajectory_parity_1e3_steps(gpu, orc, scheme):
+    res, (x, v, e, xs), (mean, se, hist) = _run_pair(orc, BASE, 1024, 1000, scheme)
+    err = mixed_err(_gpu_xve(res), (x, v, e))
+    print(f"{scheme} 1e3: p50={np.median(err):.2e} p99.9={np.quantile(err, 0.999):.2e} "
+          f"max={err.max():.2e}")
+    assert (err <= 1e-4).mean() >= 0.999
+    assert err.max() <= 1e-3
+    assert abs(res.mean_v - mean) <= 1e-5
+
+
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_ensemble_parity_1e4_steps(gpu, orc, scheme):
+    """The 1024-particle, 1e4-step, dt = 1e-3 workload (EM is the parity configuration)."""
+    n, steps = 1024, 10_000
+    res, (x, v, e, xs), (mean, se, hist) = _run_pair(orc, BASE, n, steps, scheme)
+    err = mixed_err(_gpu_xve(res), (x, v, e))
+    x0, v0, e0 = orc.init_state(n, 42)
+    sid = 0 if scheme == "em" else 1
+    xp, vp, ep, _, _ = orc.integrate(BASE, x0, v0, e0, steps, scheme=sid, seed=42,
+                                     eps=2.0**-24)
+    own = mixed_err((xp, vp, ep), (x, v, e))
+    q = [0.5, 0.9, 0.99]
+    gq, oq = np.quantile(err, q), np.quantile(own, q)
+    print(f"{scheme} 1e4: gpu-vs-oracle p50/p90/p99 = {gq}, oracle self-divergence = {oq}, "
+          f"frac<=1e-4: {(err <= 1e-4).mean():.3f}; <v> gpu={res.mean_v:.6e} ora={mean:.6e}")
+    assert np.median(err) <= 1e-4
+    assert np.all(gq <= 2 * oq + 1e-6)
+    assert abs(res.mean_v - mean) <= 1e-5
+    assert res.stderr == pytest.approx(se, rel=0.05)
+    # histogram: identical bins wherever the trajectories agree (and are off bin edges)
+    hg = _np(res.hist).astype(np.int64)
+    assert hg.sum() == n
+    xg = _np(res.state.x64())
+    bg = np.minimum(np.floor((xg - np.floor(xg)) * 256), 255).astype(np.int64)
+    bo = np.minimum(np.floor((x - np.floor(x)) * 256), 255).astype(np.int64)
+    np.testing.assert_array_equal(np.bincount(bg, minlength=256), hg)
+    frac = x - np.floor(x)
+    edge = np.minimum(np.abs(frac * 256 - np.round(frac * 256)), 1.0) / 256
+    agree = (np.abs(xg - x) < 1e-6) & (edge > 1e-6)
+    assert np.array_equal(bg[agree], bo[agree])
+    assert np.abs(hg - hist.astype(np.int64)).sum() <= 2 * (bg != bo).sum()
+
+
+def test_deterministic_limit_matches_oracle(gpu, orc):
+    p = dict(BASE, D=0.0)
+    res, (x, v, e, xs), _ = _run_pair(orc, p, 256, 2000, "heun")
+    err = mixed_err(_gpu_xve(res), (x, v, e))
+    assert err.max() <= 1e-4
+
+
+@pytest.mark.parametrize("params", [dict(U0=0.0, d2=0.0, F0=0.5, D=0.3),
+                                    dict(U0=0.3, a=0.4, phi=0.1903, F0=-0.2, d2=1.7, c=0.3,
+                                         q=0.8, gamma0=1.3, D=0.02)])
+def test_other_parameters(gpu, orc, params):
+    res, (x, v, e, xs), (mean, se, hist) = _run_pair(orc, params, 2048, 1000, "em", seed=5)
+    err = mixed_err(_gpu_xve(res), (x, v, e))
+    assert (err <= 1e-4).mean() >= 0.999 and err.max() <= 1e-3
+    assert abs(res.mean_v - mean) <= 1e-5
+
+
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_chunked_equals_unchunked_bitwise(gpu, scheme):
+    from paper_1104_2499_amd import api
+
+    n, bins = 3001, 64
+    one = api.run(BASE, n=n, steps=1003, window=502, scheme=scheme, seed=9, bins=bins)
+    s = api.init_state(n, 9)
+    snap = api.State.empty(n)
+    ws = api.reduce_workspace(n, bins)
+    for step0, k in ((0, 333), (333, 170), (503, 497), (1000, 3)):
+        last = step0 + k == 1003
+        api.integrate(s, k, BASE, scheme=scheme, seed=9, step0=step0, win_begin=501, snap=snap,
+                      ws=ws if last else None, n_bins=bins)
+    out, hist = api.reduce(ws, n, bins, 502e-3)
+    for a_, b_ in ((one.state.cell, s.cell), (one.state.xf, s.xf), (one.state.v, s.v),
+                   (one.state.e, s.e), (one.snap.xf, snap.xf), (one.snap.cell, snap.cell)):
+        assert torch.equal(a_, b_)
+    assert float(out[0].cpu()) == one.mean_v and float(out[1].cpu()) == one.stderr
+    assert torch.equal(hist, one.hist)
+
+
+def test_every_tuning_gives_identical_results(gpu):
+    from paper_1104_2499_amd import api
+
+    ref = None
+    for block in (64, 128, 256):
+        for ppl in (1, 2):
+            for unroll in (1, 2):
+                r = api.run(BASE, n=5000, steps=403, window=201, scheme="heun", seed=3, bins=128,
+                            tune=dict(block=block, ppl=ppl, unroll=unroll))
+                got = (_np(r.state.cell), _np(r.state.xf), _np(r.state.v), _np(r.state.e),
+                       r.mean_v, r.stderr, _np(r.hist))
+                if ref is None:
+                    ref = got
+                    continue
+                for a_, b_ in zip(ref, got):
+                    np.testing.assert_array_equal(a_, b_)
+
+
+def test_reduce_state_histogram_bit_exact(gpu, orc):
+    from paper_1104_2499_amd import api
+
+    rng = np.random.default_rng(4)
+    n = 100_003
+    cell = rng.integers(-1000, 1000, n).astype(np.int32)
+    xf = rng.random(n).astype(np.float32)
+    edges = (np.arange(256) / 256).astype(np.float32)
+    xf[:256] = edges                                        # exactly on bin edges
+    xf[256:512] = np.nextafter(edges, np.float32(-1))       # just below them
+    xf[512:520] = [0.0, -0.0, 1.0, -1e-30, 1.0 - 2**-24, -0.5, 1.5, -2**-26]
+    scell = rng.integers(-10, 10, n).astype(np.int32)
+    sxf = rng.random(n).astype(np.float32)
+    end = api.State(torch.from_numpy(cell).cuda(), torch.from_numpy(xf).cuda(),
+                    torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"))
+    snap = api.State(torch.from_numpy(scell).cuda(), torch.from_numpy(sxf).cuda(),
+                     torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"))
+    for bins in (256, 4096, 1):
+        ws = api.reduce_workspace(n, bins)
+        api.reduce_state(snap, end, bins, ws)
+        out, hist = api.reduce(ws, n, bins, 3.5)
+        xe = cell.astype(np.float64) + xf.astype(np.float64)
+        xs = scell.astype(np.float64) + sxf.astype(np.float64)
+        mean, se, h = orc.reduce(xs, xe, 3.5, bins)
+        np.testing.assert_array_equal(_np(hist).astype(np.uint64), h)
+        assert float(out[0].cpu()) == pytest.approx(mean, rel=1e-12)
+        assert float(out[1].cpu()) == pytest.approx(se, rel=1e-9)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 129])
+def test_ragged_sizes(gpu, orc, n):
+    res, (x, v, e, xs), (mean, se, hist) = _run_pair(orc, BASE, n, 401, "em", seed=1, window=7)
+    err = mixed_err(_gpu_xve(res), (x, v, e))
+    assert err.max() <= 1e-4
+    assert abs(res.mean_v - mean) <= 1e-5 * max(1.0, abs(mean))
+    assert int(_np(res.hist).sum()) == n
+
+
+def test_zero_steps_and_partial_blocks(gpu, orc):
+    from paper_1104_2499_amd import api
+
+    n = 100
+    s = api.init_state(n, 2)
+    before = s.clone()
+    snap = api.State.empty(n)
+    ws = api.reduce_workspace(n, 16)
+    api.integrate(s, 0, BASE, step0=6, win_begin=6, snap=snap, ws=ws, n_bins=16)
+    out, hist = api.reduce(ws, n, 16, 1.0)
+    assert torch.equal(s.xf, before.xf) and torch.equal(snap.xf, before.xf)
+    assert float(out[0].cpu()) == 0.0 and int(hist.sum().cpu()) == n
+    # 2 steps inside one Philox block, starting mid-block
+    api.integrate(s, 2, BASE, step0=5, seed=2)
+    x0, v0, e0 = orc.init_state(n, 2)
+    x, v, e, _, _ = orc.integrate(BASE, x0, v0, e0, 2, step0=5, seed=2)
+    err = mixed_err((_np(s.x64()), _np(s.v), _np(s.e)), (x, v, e))
+    assert err.max() <= 1e-6
+
+
+def test_invalid_arguments_raise(gpu):
+    from paper_1104_2499_amd import api
+
+    s = api.init_state(64, 1)
+    with pytest.raises(api.AbpError, match="ABP_E_ARG"):
+        api.integrate(s, 10, dict(BASE, D=-1.0))
+    with pytest.raises(api.AbpError, match="ABP_E_WORKSPACE"):
+        api.integrate(s, 10, BASE, win_begin=0, snap=api.State.empty(64),
+                      ws=torch.empty(16, dtype=torch.uint8, device="cuda"), n_bins=256)
+
+
+def test_full_size_heun_sampled(gpu, orc):
+    """2^20 particles, stochastic Heun, in the launch shape the benchmark times: sampled particles
+    (first, last, spread) match the oracle one by one after 1e3 steps, and the long-run ensemble
+    mean agrees statistically with an oracle sub-ensemble."""
+    from paper_1104_2499_amd import api
+
+    n = 1 << 20
+    res = api.run(BASE, n=n, steps=1000, window=500, scheme="heun", seed=7, bins=256)
+    ids = np.unique(np.concatenate([[0, 1, 63, 64, n - 65, n - 1],
+                                    np.random.default_rng(0).integers(0, n, 250)]))
+    x0, v0, e0 = orc.init_state(ids.size, 7, ids=ids)
+    x, v, e, _, _ = orc.integrate(BASE, x0, v0, e0, 1000, scheme=1, seed=7, ids=ids)
+    idx = torch.from_numpy(ids.astype(np.int64)).cuda()
+    g = (_np(res.state.x64()[idx]), _np(res.state.v[idx]), _np(res.state.e[idx]))
+    err = mixed_err(g, (x, v, e))
+    assert err.max() <= 1e-3 and np.median(err) <= 1e-5
+    assert int(_np(res.hist).sum()) == n
+
+    steps, window = 20_000, 10_000
+    big = api.run(BASE, n=n, steps=steps, window=window, scheme="heun", seed=7, bins=256)
+    m = 4096
+    sub = np.arange(m, dtype=np.uint64) * (n // m)
+    x0, v0, e0 = orc.init_state(m, 7, ids=sub)
+    x, v, e, xs, _ = orc.integrate(BASE, x0, v0, e0, steps, scheme=1, seed=7, ids=sub,
+                                   win_begin=steps - window)
+    mean, se, _ = orc.reduce(xs, x, window * 1e-3, 256)
+    assert abs(big.mean_v - mean) <= 4 * np.hypot(big.stderr, se)
+    assert int(_np(big.hist).sum()) == n
