@@ -12,10 +12,10 @@
  *
  * Noise contract. Philox4x32-10 (Salmon et al., SC'11) with key (seed mod 2^32, seed / 2^32) and
  * counter (n / 4, particle id, set id, 0) for absolute step n; the four words of one block become
- * four normals by Box-Muller (Fig. 1) on 24-bit uniforms u1 = ((w0 >> 8) + 1) 2^-24,
- * u2 = (w1 >> 8) 2^-24: z0 = rho cos 2pi u2, z1 = rho sin 2pi u2, rho = sqrt(-2 ln u1), and
- * likewise (w2, w3) -> z2, z3. Step n uses z[n mod 4]. Initial positions: x0 = (w0 >> 8) 2^-24 of
- * block (0, particle id, set id, 1); v0 = e0 = 0.
+ * four normals by Box-Muller (Fig. 1) on 23-bit uniforms u1 = 1 - (w0 >> 9) 2^-23 in (0, 1],
+ * u2 = (w1 >> 9) 2^-23 in [0, 1): z0 = rho cos 2pi u2, z1 = rho sin 2pi u2, rho = sqrt(-2 ln u1),
+ * and likewise (w2, w3) -> z2, z3. Step n uses z[n mod 4]. Initial positions: x0 = (w0 >> 8) 2^-24
+ * of block (0, particle id, set id, 1); v0 = e0 = 0.
  *
  * Conventions for every entry point:
  *  - Pointers named d_* are HIP device memory owned by the caller; h_* are host memory; structs
@@ -70,16 +70,20 @@ typedef struct abp_run {
 } abp_run;
 /* step0 + n_steps must not exceed 2^34 (the block counter n/4 is one 32-bit word). */
 
-/* Particle state in structure-of-arrays form, device memory, n entries each. The position is
- * x = cell + xf with an integer cell and an FP32 fraction xf (kept near [0, 1)), so FP32 never
- * adds a small increment to a large coordinate. Particle i has Philox id id0 + i. */
+/* Particle state in structure-of-arrays form, device memory. Sec. 2 of the paper asks single
+ * precision to avoid adding very small numbers to very big ones; the state is therefore kept as
+ * FP32 high/low pairs: x = cell + xf + lx with an integer cell and xf in [0, 1), v = v + lv,
+ * e = e + le. d_lo holds 3n floats: lx at [0, n), lv at [n, 2n), le at [2n, 3n). The low parts
+ * are part of the state (a run split into calls is bit-identical to one call only if they are
+ * carried). Particle i has Philox id id0 + i. */
 typedef struct abp_state {
-    int32_t *d_cell;
-    float *d_xf;
-    float *d_v;
-    float *d_e;
-    int64_t n;     /* >= 1, <= 2^31 */
-    uint32_t id0;  /* id of particle 0; id0 + n - 1 must fit in 32 bits */
+    int32_t *d_cell;  /* n */
+    float *d_xf;      /* n */
+    float *d_v;       /* n */
+    float *d_e;       /* n */
+    float *d_lo;      /* 3n */
+    int64_t n;        /* >= 1, <= 2^31 */
+    uint32_t id0;     /* id of particle 0; id0 + n - 1 must fit in 32 bits */
     uint32_t pad;
 } abp_state;
 
@@ -109,8 +113,9 @@ size_t abp_reduce_workspace_bytes(int64_t n, int32_t n_bins);
 /* Advance the ensemble by r->n_steps steps of the chosen scheme (Eqs. (1)-(3); the per-step loop
  * of Fig. 1), in place on *s. Euler-Maruyama evaluates all drifts at the old state; Heun averages
  * the drifts at the old state and at the Euler predictor, with the same normal.
- *  snap: where the window snapshot (cell, xf) is written when step0 <= win_begin <= step0+n_steps
- *        and read from when win_begin < step0; may be NULL if win_begin < 0. v and e unused.
+ *  snap: state copy written at time index win_begin when step0 <= win_begin <= step0+n_steps,
+ *        and read (its position) when the window opened in an earlier call; may be NULL when
+ *        neither happens.
  *  d_ws: if non-NULL, the call also reduces the ensemble at its end: per-tile FP64 sums of the
  *        window displacement and its square, and the histogram of x mod 1 (n_bins bins), are
  *        written to d_ws (ws_bytes >= abp_reduce_workspace_bytes(n, n_bins)); abp_reduce turns
@@ -123,7 +128,8 @@ abp_status abp_integrate(const abp_params *p, const abp_run *r, const abp_state 
 /* Finish a reduction left in d_ws by abp_integrate or abp_reduce_state for n particles:
  * d_out[0] = mean drift velocity = sum(delta) / (n window_time), d_out[1] = its standard error,
  * d_hist[n_bins] = u64 counts of particles with floor(n_bins (x - floor x)) = b (clamped to
- * n_bins - 1), x = cell + xf evaluated in FP64. d_hist may be NULL when n_bins = 0. */
+ * n_bins - 1), x = (cell + xf) + lx evaluated in FP64; delta is the same FP64 position at the end
+ * minus that of the snapshot. d_hist may be NULL when n_bins = 0. */
 abp_status abp_reduce(const void *d_ws, int64_t n, int32_t n_bins, double window_time,
                       double *d_out, uint64_t *d_hist, void *stream);
 
@@ -131,6 +137,36 @@ abp_status abp_reduce(const void *d_ws, int64_t n, int32_t n_bins, double window
  * into d_ws as abp_integrate does. */
 abp_status abp_reduce_state(const abp_state *snap, const abp_state *end, int32_t n_bins,
                             void *d_ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batched sweep: many parameter sets, each an ensemble of its own size and step count, in one
+ * persistent launch (Sec. 2 runs one work item per parameter set concurrently).
+ * ------------------------------------------------------------------------------------------- */
+typedef struct abp_batch {
+    double dt;        /* time step shared by all sets, > 0 */
+    uint64_t seed;    /* Philox key shared by all sets; set k uses counter word 2 = k */
+    int32_t scheme;   /* abp_scheme */
+    int32_t n_bins;   /* histogram bins per set: 0 or a power of two up to 4096 */
+} abp_batch;
+
+/* Bytes of workspace for abp_integrate_batched (0 if the sizes are invalid). */
+size_t abp_batched_workspace_bytes(int32_t n_sets, const int32_t *h_ntraj, int32_t n_bins);
+
+/* Integrate n_sets independent ensembles and reduce each one. Set k has parameters h_params[k],
+ * h_ntraj[k] >= 1 particles (ids 0..h_ntraj[k]-1, Philox set id k) started from the workload
+ * initial condition, h_nsteps[k] >= 1 steps, and a window of the last h_window[k] steps
+ * (1 <= window <= steps; h_window NULL = h_nsteps[k] / 2). Outputs: d_out[2k], d_out[2k+1] =
+ * mean drift velocity and its standard error; d_hist[k n_bins + b] = u64 histogram of the final
+ * x mod 1. Each set's results equal, bit for bit, those of abp_init_state + abp_integrate +
+ * abp_reduce run on that set alone with set_id = k, for every tuning. The host arrays are read
+ * during the call; per-set constants and the work list are staged into d_ws, so the call returns
+ * only after the stream has drained (it cannot be captured into a graph). tune: block, ppl,
+ * unroll and waves_per_simd (grid = CUs x 4 x waves_per_simd waves); NULL = default. */
+abp_status abp_integrate_batched(int32_t n_sets, const abp_params *h_params,
+                                 const int32_t *h_ntraj, const int64_t *h_nsteps,
+                                 const int64_t *h_window, const abp_batch *cfg,
+                                 const abp_tuning *tune, void *d_ws, size_t ws_bytes,
+                                 double *d_out, uint64_t *d_hist, void *stream);
 
 #ifdef __cplusplus
 }

@@ -80,16 +80,17 @@ static void philox_for(uint64_t seed, uint32_t blk, uint32_t pid, uint32_t set, 
     orc_philox4x32_10(ctr, key, r);
 }
 
-/* Box-Muller (the transformation named in Fig. 1): 24-bit uniforms u1 in (0,1], u2 in [0,1),
- * rho = sqrt(-2 ln u1), z = (rho cos 2pi u2, rho sin 2pi u2). Words (r0,r1) give z0,z1 and
- * (r2,r3) give z2,z3; step n of a particle uses z[n mod 4] of block n/4. */
+/* Box-Muller (the transformation named in Fig. 1): 23-bit uniforms u1 = 1 - (r >> 9) 2^-23 in
+ * (0,1] and u2 = (r' >> 9) 2^-23 in [0,1), rho = sqrt(-2 ln u1), z = (rho cos 2pi u2,
+ * rho sin 2pi u2). Words (r0,r1) give z0,z1 and (r2,r3) give z2,z3; step n of a particle uses
+ * z[n mod 4] of block n/4. */
 static void normals4(uint64_t seed, uint32_t pid, uint32_t set, uint32_t blk, double z[4])
 {
     uint32_t r[4];
     philox_for(seed, blk, pid, set, DOMAIN_NOISE, r);
     for (int pair = 0; pair < 2; ++pair) {
-        double u1 = (double)((r[2 * pair] >> 8) + 1u) * 0x1p-24;
-        double u2 = (double)(r[2 * pair + 1] >> 8) * 0x1p-24;
+        double u1 = 1.0 - (double)(r[2 * pair] >> 9) * 0x1p-23;
+        double u2 = (double)(r[2 * pair + 1] >> 9) * 0x1p-23;
         double rho = sqrt(-2.0 * log(u1));
         z[2 * pair] = rho * cos(2.0 * ORC_PI * u2);
         z[2 * pair + 1] = rho * sin(2.0 * ORC_PI * u2);

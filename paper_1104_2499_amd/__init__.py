@@ -7,10 +7,10 @@ end. Submodules: ``api`` (integrate / reduce / run), ``workloads`` (seeded synth
 from importlib import import_module
 
 __all__ = ["api", "workloads", "build", "State", "init_state", "integrate", "reduce",
-           "reduce_state", "run", "philox", "AbpError"]
+           "reduce_state", "run", "philox", "sweep", "AbpError"]
 
 _API_NAMES = {"State", "init_state", "integrate", "reduce", "reduce_state", "run", "philox",
-              "AbpError", "reduce_workspace", "Result"}
+              "AbpError", "reduce_workspace", "Result", "sweep", "SweepResult", "reset_state"}
 
 
 def __getattr__(name):

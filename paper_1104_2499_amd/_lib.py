@@ -30,13 +30,18 @@ class AbpRun(ctypes.Structure):
 
 class AbpState(ctypes.Structure):
     _fields_ = [("d_cell", ctypes.c_void_p), ("d_xf", ctypes.c_void_p), ("d_v", ctypes.c_void_p),
-                ("d_e", ctypes.c_void_p), ("n", ctypes.c_int64), ("id0", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("d_e", ctypes.c_void_p), ("d_lo", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("id0", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 
 class AbpTuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("ppl", ctypes.c_int32), ("unroll", ctypes.c_int32),
                 ("waves_per_simd", ctypes.c_int32)]
+
+
+class AbpBatch(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("seed", ctypes.c_uint64), ("scheme", ctypes.c_int32),
+                ("n_bins", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER
@@ -55,6 +60,9 @@ SIGNATURES = {
                                      _sz, _i32, _P(AbpTuning), _vp]),
     "abp_reduce": (ctypes.c_int, [_vp, _i64, _i32, _f64, _vp, _vp, _vp]),
     "abp_reduce_state": (ctypes.c_int, [_P(AbpState), _P(AbpState), _i32, _vp, _sz, _vp]),
+    "abp_batched_workspace_bytes": (_sz, [_i32, _vp, _i32]),
+    "abp_integrate_batched": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _P(AbpBatch),
+                                             _P(AbpTuning), _vp, _sz, _vp, _vp, _vp]),
 }
 
 

@@ -11,6 +11,8 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
+import numpy as np
+
 from .workloads import BASE_PARAMS, PARAM_KEYS
 
 SCHEMES = {"em": _lib.ABP_EM, "heun": _lib.ABP_HEUN}
@@ -66,11 +68,13 @@ def make_tuning(tune) -> _lib.AbpTuning | None:
 
 @dataclass
 class State:
-    """Structure-of-arrays particle state on the device: x = cell + xf."""
+    """Structure-of-arrays particle state on the device, FP32 high/low pairs:
+    x = cell + xf + lo[0], v = v + lo[1], e = e + lo[2] (lo has shape [3, n])."""
     cell: torch.Tensor
     xf: torch.Tensor
     v: torch.Tensor
     e: torch.Tensor
+    lo: torch.Tensor
     id0: int = 0
 
     @property
@@ -79,25 +83,36 @@ class State:
 
     @staticmethod
     def empty(n: int, device="cuda", id0: int = 0) -> "State":
-        return State(torch.empty(n, dtype=torch.int32, device=device),
-                     torch.empty(n, dtype=torch.float32, device=device),
-                     torch.empty(n, dtype=torch.float32, device=device),
-                     torch.empty(n, dtype=torch.float32, device=device), id0)
+        f = dict(dtype=torch.float32, device=device)
+        return State(torch.empty(n, dtype=torch.int32, device=device), torch.empty(n, **f),
+                     torch.empty(n, **f), torch.empty(n, **f), torch.empty((3, n), **f), id0)
 
     def clone(self) -> "State":
-        return State(self.cell.clone(), self.xf.clone(), self.v.clone(), self.e.clone(), self.id0)
+        return State(self.cell.clone(), self.xf.clone(), self.v.clone(), self.e.clone(),
+                     self.lo.clone(), self.id0)
+
+    def tensors(self):
+        return (self.cell, self.xf, self.v, self.e, self.lo)
 
     def abi(self) -> _lib.AbpState:
-        for t, dt in ((self.cell, torch.int32), (self.xf, torch.float32), (self.v, torch.float32),
-                      (self.e, torch.float32)):
-            if t.dtype != dt or not t.is_contiguous() or t.numel() != self.n:
-                raise ValueError("state tensors must be contiguous int32/float32 of equal length")
+        n = self.n
+        for t, dt, k in ((self.cell, torch.int32, n), (self.xf, torch.float32, n),
+                         (self.v, torch.float32, n), (self.e, torch.float32, n),
+                         (self.lo, torch.float32, 3 * n)):
+            if t.dtype != dt or not t.is_contiguous() or t.numel() != k:
+                raise ValueError("state tensors must be contiguous int32/float32 of sizes n,n,n,n,3n")
         return _lib.AbpState(self.cell.data_ptr(), self.xf.data_ptr(), self.v.data_ptr(),
-                             self.e.data_ptr(), self.n, self.id0, 0)
+                             self.e.data_ptr(), self.lo.data_ptr(), n, self.id0, 0)
 
     def x64(self) -> torch.Tensor:
-        """Positions cell + xf in float64 (on the state's device)."""
-        return self.cell.double() + self.xf.double()
+        """Positions (cell + xf) + lx in float64, as the library evaluates them."""
+        return (self.cell.double() + self.xf.double()) + self.lo[0].double()
+
+    def v64(self) -> torch.Tensor:
+        return self.v.double() + self.lo[1].double()
+
+    def e64(self) -> torch.Tensor:
+        return self.e.double() + self.lo[2].double()
 
 
 def reset_state(s: State, seed: int, set_id: int = 0, stream=None) -> State:
@@ -191,3 +206,58 @@ def run(params: dict | None = None, n: int = 1024, steps: int = 10_000, window: 
     out, hist = reduce(ws, n, bins, window * dt, stream)
     o = out.cpu()
     return Result(float(o[0]), float(o[1]), hist, st, snap)
+
+
+@dataclass
+class SweepResult:
+    mean_v: np.ndarray   # [n_sets] float64
+    stderr: np.ndarray   # [n_sets] float64
+    hist: torch.Tensor   # [n_sets, n_bins] int64 (u64 counts) on the device
+
+
+def params_table(table) -> np.ndarray:
+    """[n_sets, 9] float64 in PARAM_KEYS order from an array or a list of dicts."""
+    if isinstance(table, np.ndarray):
+        t = np.ascontiguousarray(table, dtype=np.float64)
+    else:
+        t = np.array([[float(dict(BASE_PARAMS, **row)[k]) for k in PARAM_KEYS] for row in table],
+                     dtype=np.float64)
+    if t.ndim != 2 or t.shape[1] != len(PARAM_KEYS):
+        raise ValueError("parameter table must be [n_sets, 9]")
+    return t
+
+
+def batched_workspace(n_traj, n_bins: int, device="cuda") -> torch.Tensor:
+    nt = np.ascontiguousarray(n_traj, dtype=np.int32)
+    nbytes = int(_lib.load().abp_batched_workspace_bytes(nt.size, nt.ctypes.data, n_bins))
+    if nbytes == 0:
+        raise ValueError("invalid batched sweep sizes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def sweep(table, n_traj, n_steps, window=None, dt: float = 1e-3, scheme="em", seed: int = 11,
+          bins: int = 256, tune=None, ws: torch.Tensor | None = None, device="cuda",
+          stream=None) -> SweepResult:
+    """One persistent launch over many parameter sets (abp_integrate_batched). Set k runs
+    n_traj[k] particles for n_steps[k] steps with Philox set id k and averages over the last
+    window[k] steps (default n_steps[k] // 2)."""
+    t = params_table(table)
+    n_sets = t.shape[0]
+    nt = np.ascontiguousarray(n_traj, dtype=np.int32)
+    ns = np.ascontiguousarray(n_steps, dtype=np.int64)
+    if nt.shape != (n_sets,) or ns.shape != (n_sets,):
+        raise ValueError("n_traj and n_steps need one entry per set")
+    win = None if window is None else np.ascontiguousarray(window, dtype=np.int64)
+    if ws is None:
+        ws = batched_workspace(nt, bins, device)
+    out = torch.empty((n_sets, 2), dtype=torch.float64, device=device)
+    hist = torch.empty((n_sets, max(bins, 1)), dtype=torch.int64, device=device)
+    cfg = _lib.AbpBatch(dt, seed, scheme_id(scheme), bins)
+    tn = make_tuning(tune)
+    check(_lib.load().abp_integrate_batched(
+        n_sets, t.ctypes.data, nt.ctypes.data, ns.ctypes.data,
+        None if win is None else win.ctypes.data, ctypes.byref(cfg),
+        ctypes.byref(tn) if tn is not None else None, _ptr(ws), ws.numel(), _ptr(out),
+        _ptr(hist) if bins > 0 else None, _stream(stream)), "abp_integrate_batched")
+    o = out.cpu().numpy()
+    return SweepResult(o[:, 0].copy(), o[:, 1].copy(), hist[:, :bins])

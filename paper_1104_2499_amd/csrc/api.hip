@@ -1,6 +1,7 @@
 // api.hip -- library-wide entry points: version and status strings, the device check, the
 // initial condition and the raw Philox generator.
 #include "common.hpp"
+#include "reduce.hpp"
 
 namespace abp {
 
@@ -23,8 +24,8 @@ abp_status check_device()
 
 // x0 = (w0 >> 8) 2^-24 of Philox block (0, id, set, 1); v0 = e0 = 0.
 __global__ __launch_bounds__(256) void k_init_state(int32_t *cell, float *xf, float *v, float *e,
-                                                    int64_t n, uint32_t id0, uint32_t set,
-                                                    uint32_t k0, uint32_t k1)
+                                                    float *lo, int64_t n, uint32_t id0,
+                                                    uint32_t set, uint32_t k0, uint32_t k1)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
@@ -34,6 +35,16 @@ __global__ __launch_bounds__(256) void k_init_state(int32_t *cell, float *xf, fl
     xf[i] = (float)(r.w[0] >> 8) * 0x1p-24f;
     v[i] = 0.0f;
     e[i] = 0.0f;
+    lo[i] = 0.0f;
+    lo[n + i] = 0.0f;
+    lo[2 * n + i] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        p[i] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_philox(int64_t m, const uint32_t *ctr,
@@ -78,7 +89,7 @@ extern "C" abp_status abp_init_state(const abp_state *s, uint64_t seed, uint32_t
     const Stream ks = make_stream(seed, set_id);
     const unsigned grid = (unsigned)((s->n + 255) / 256);
     hipLaunchKernelGGL(k_init_state, dim3(grid), dim3(256), 0, as_stream(stream), s->d_cell,
-                       s->d_xf, s->d_v, s->d_e, s->n, s->id0, set_id, ks.k0, ks.k1);
+                       s->d_xf, s->d_v, s->d_e, s->d_lo, s->n, s->id0, set_id, ks.k0, ks.k1);
     return launch_status();
 }
 

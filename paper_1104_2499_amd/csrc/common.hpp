@@ -67,10 +67,10 @@ inline Stream make_stream(uint64_t seed, uint32_t set)
 
 inline bool state_ok(const abp_state *s)
 {
-    if (!s || !s->d_cell || !s->d_xf || !s->d_v || !s->d_e)
+    if (!s || !s->d_cell || !s->d_xf || !s->d_v || !s->d_e || !s->d_lo)
         return false;
     if (!aligned(s->d_cell, 4) || !aligned(s->d_xf, 4) || !aligned(s->d_v, 4) ||
-        !aligned(s->d_e, 4))
+        !aligned(s->d_e, 4) || !aligned(s->d_lo, 4))
         return false;
     if (s->n < 1 || s->n > kMaxParticles)
         return false;

@@ -56,21 +56,26 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 enum : uint32_t { kDomainNoise = 0u, kDomainInit = 1u };
 
 // ---------------------------------------------------------------------------------------------
-// Box-Muller on 24-bit uniforms, with the noise amplitude folded in: returns sigma*z0, sigma*z1.
-// u1 = (m+1) 2^-24 in (0, 1] and u2 = m' 2^-24 in [0, 1) are exact in FP32. The hardware
-// transcendentals are used directly: v_log_f32 is log2, and v_sin_f32 / v_cos_f32 take their
-// argument in revolutions, so sin(2 pi u2) is v_sin_f32(u2) with no range reduction.
+// Box-Muller on 23-bit uniforms, with the noise amplitude folded in: returns sigma*z0, sigma*z1.
+// One v_alignbit_b32 turns a Philox word w into y = 1 + (w >> 9) 2^-23 in [1, 2) (the word's top
+// 23 bits under the exponent of 1.0). Then u1 = 2 - y1 in (0, 1] exactly, and because v_sin_f32 /
+// v_cos_f32 take their argument in revolutions (period 1), sin(2 pi u2) = v_sin_f32(y2) with
+// u2 = y2 - 1 in [0, 1). v_log_f32 is log2, so -2 ln u1 = -2 ln2 * log2 u1.
 // ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ float unit_interval_1_2(uint32_t w)
+{
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9u));
+}
+
 __device__ __forceinline__ void box_muller_scaled(uint32_t wa, uint32_t wb, float sigma,
                                                   float &za, float &zb)
 {
-    const float u1 = (float)((wa >> 8) + 1u) * 0x1p-24f;
-    const float u2 = (float)(wb >> 8) * 0x1p-24f;
+    const float u1 = 2.0f - unit_interval_1_2(wa);
+    const float y2 = unit_interval_1_2(wb);
     const float minus_2ln2 = -1.38629436111989061883f;
-    const float rho = __builtin_amdgcn_sqrtf(minus_2ln2 * __builtin_amdgcn_logf(u1));
-    const float s = sigma * rho;
-    za = s * __builtin_amdgcn_cosf(u2);
-    zb = s * __builtin_amdgcn_sinf(u2);
+    const float s = sigma * __builtin_amdgcn_sqrtf(minus_2ln2 * __builtin_amdgcn_logf(u1));
+    za = s * __builtin_amdgcn_cosf(y2);
+    zb = s * __builtin_amdgcn_sinf(y2);
 }
 
 // Noise block b of particle `pid`: sigma * (z0, z1, z2, z3) for steps 4b .. 4b+3.
@@ -89,9 +94,10 @@ __device__ __forceinline__ Noise4 noise_block(uint32_t blk, uint32_t pid, uint32
 }
 
 // ---------------------------------------------------------------------------------------------
-// Drift of Eqs. (1)-(3) in FP32, wavefront-uniform coefficients.
-//   U'(x) = 2 pi U0 [cos th + 2a cos 2th], th = 2 pi (x + phi); with c = cos th and the double
-//   angle cos 2th = 2c^2 - 1:  F0 - U'(x) = (F0 + 4 pi U0 a) - c (2 pi U0 + 8 pi U0 a c).
+// Drift of Eqs. (1)-(3) in FP32, wavefront-uniform coefficients, at the phase-shifted position
+// xs = x + phi (in revolutions: only its fractional part matters).
+//   U'(x) = 2 pi U0 [cos th + 2a cos 2th], th = 2 pi xs; with c = cos th and the double angle
+//   cos 2th = 2c^2 - 1:  F0 - U'(x) = (F0 + 4 pi U0 a) - c (2 pi U0 + 8 pi U0 a c).
 //   f_v = F0 - U'(x) + (d2 e - gamma0) v,   f_e = q - e (c + d2 v^2).
 // ---------------------------------------------------------------------------------------------
 struct Coef {
@@ -102,61 +108,84 @@ struct Coef {
     float g0, d2, q, c;
 };
 
-__device__ __forceinline__ void drift(const Coef &k, float xf, float v, float e, float &fv,
+__device__ __forceinline__ void drift(const Coef &k, float xs, float v, float e, float &fv,
                                       float &fe)
 {
-    const float cth = __builtin_amdgcn_cosf(xf + k.phi);
+    const float cth = __builtin_amdgcn_cosf(xs);
     const float fu = fmaf(-cth, fmaf(k.B, cth, k.K1), k.FH);
     fv = fmaf(fmaf(k.d2, e, -k.g0), v, fu);
     fe = fmaf(-e, fmaf(k.d2 * v, v, k.c), k.q);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Particle state as a float-float pair per coordinate (the single-precision remedy for adding
+// small increments to large values): x = cell + xf + lx, v = v + lv, e = e + le.
+// Within an aligned block of four steps the high parts (cell, xf, v, e) stay fixed and every
+// increment goes into the low part, which starts the block holding the previous rounding error;
+// after the block's last step each pair is renormalised by Fast2Sum (exact: the high part
+// dominates) and xf is wrapped back into [0, 1) with its rounding error kept in lx. The drift sees
+// the rounded sums (high + low). A state stored mid-block is resumed bit for bit.
+// ---------------------------------------------------------------------------------------------
 struct Particle {
     int32_t cell;
     float xf, v, e;
+    float lx, lv, le;
 };
 
-// Euler-Maruyama: every drift at the old state; zs = sigma * xi_n.
-__device__ __forceinline__ void step_em(const Coef &k, Particle &p, float zs)
+// Euler-Maruyama: every drift at the old state; zs = sigma * xi_n; xb = xf + phi of the block.
+__device__ __forceinline__ void step_em(const Coef &k, Particle &p, float xb, float zs)
 {
+    const float xc = xb + p.lx, vc = p.v + p.lv, ec = p.e + p.le;
     float fv, fe;
-    drift(k, p.xf, p.v, p.e, fv, fe);
-    p.xf = fmaf(p.v, k.dt, p.xf);
-    p.v = p.v + fmaf(fv, k.dt, zs);
-    p.e = fmaf(fe, k.dt, p.e);
+    drift(k, xc, vc, ec, fv, fe);
+    p.lx = fmaf(vc, k.dt, p.lx);
+    p.lv = p.lv + fmaf(fv, k.dt, zs);
+    p.le = fmaf(fe, k.dt, p.le);
 }
 
 // Stochastic Heun for additive noise: Euler predictor with the same normal, then the
 // trapezoidal average of the two drifts.
-__device__ __forceinline__ void step_heun(const Coef &k, Particle &p, float zs)
+__device__ __forceinline__ void step_heun(const Coef &k, Particle &p, float xb, float zs)
 {
+    const float xc = xb + p.lx, vc = p.v + p.lv, ec = p.e + p.le;
     float fv0, fe0, fv1, fe1;
-    drift(k, p.xf, p.v, p.e, fv0, fe0);
-    const float xp = fmaf(p.v, k.dt, p.xf);
-    const float vp = p.v + fmaf(fv0, k.dt, zs);
-    const float ep = fmaf(fe0, k.dt, p.e);
+    drift(k, xc, vc, ec, fv0, fe0);
+    const float xp = fmaf(vc, k.dt, xc);
+    const float vp = vc + fmaf(fv0, k.dt, zs);
+    const float ep = fmaf(fe0, k.dt, ec);
     drift(k, xp, vp, ep, fv1, fe1);
-    p.xf = fmaf(p.v + vp, k.half_dt, p.xf);
-    p.v = p.v + fmaf(fv0 + fv1, k.half_dt, zs);
-    p.e = fmaf(fe0 + fe1, k.half_dt, p.e);
+    p.lx = fmaf(vc + vp, k.half_dt, p.lx);
+    p.lv = p.lv + fmaf(fv0 + fv1, k.half_dt, zs);
+    p.le = fmaf(fe0 + fe1, k.half_dt, p.le);
 }
 
 template <int SCHEME>
-__device__ __forceinline__ void step(const Coef &k, Particle &p, float zs)
+__device__ __forceinline__ void step(const Coef &k, Particle &p, float xb, float zs)
 {
     if constexpr (SCHEME == 0)
-        step_em(k, p, zs);
+        step_em(k, p, xb, zs);
     else
-        step_heun(k, p, zs);
+        step_heun(k, p, xb, zs);
 }
 
-// Periodic bookkeeping after every aligned block of four steps: move the integer part of xf into
-// the cell. xf only leaves [0, 1) by |v| dt per step, and cos is periodic, so doing this once per
-// block keeps FP32 resolution while costing about one instruction per step.
-__device__ __forceinline__ void wrap(Particle &p)
+__device__ __forceinline__ void renorm(float &hi, float &lo)
 {
+    const float t = hi + lo;
+    lo = lo - (t - hi);
+    hi = t;
+}
+
+// End of an aligned block (after absolute step 4b+3): renormalise the pairs, then move the integer
+// part of xf into the cell; x leaves [0, 1) by at most a few |v| dt per block and cos is periodic.
+__device__ __forceinline__ void end_block(Particle &p)
+{
+    renorm(p.xf, p.lx);
+    renorm(p.v, p.lv);
+    renorm(p.e, p.le);
     const float fl = floorf(p.xf);
-    p.xf -= fl;
+    const float w = p.xf - fl;
+    p.lx += p.xf - (w + fl);  // Fast2Sum error of xf + (-fl), |fl| >= |xf| whenever fl != 0
+    p.xf = w;
     p.cell += (int32_t)fl;
 }
 
@@ -173,8 +202,9 @@ struct Stream {
 
 // Advance PPL particles of one lane from absolute step n to `stop` (both wavefront-uniform).
 // Blocks of four steps aligned on absolute indices take the fast path; a call that starts or
-// ends inside a block handles its partial block step by step. Wraps happen only after absolute
-// steps 4b+3, so any split of a run into calls gives bit-identical states.
+// ends inside a block handles its partial block step by step. Block ends (renormalisation and
+// wrap) happen only after absolute steps 4b+3, so any split of a run into calls gives
+// bit-identical states.
 template <int SCHEME, int PPL, int UNROLL>
 __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const uint32_t (&pid)[PPL],
                                         Particle (&p)[PPL], int64_t &n, int64_t stop)
@@ -187,10 +217,11 @@ __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const ui
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
             const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.sigma);
+            const float xb = p[q].xf + k.phi;
             for (uint32_t j = j0; j < j1; ++j)
-                step<SCHEME>(k, p[q], pick(z, j));
+                step<SCHEME>(k, p[q], xb, pick(z, j));
             if (j1 == 4)
-                wrap(p[q]);
+                end_block(p[q]);
         }
         n += (int64_t)(j1 - j0);
     }
@@ -204,10 +235,11 @@ __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const ui
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
                 const Noise4 z = noise_block(blk + u, pid[q], s.set, s.k0, s.k1, k.sigma);
+                const float xb = p[q].xf + k.phi;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    step<SCHEME>(k, p[q], z.z[j]);
-                wrap(p[q]);
+                    step<SCHEME>(k, p[q], xb, z.z[j]);
+                end_block(p[q]);
             }
         }
         blk += UNROLL;
@@ -216,22 +248,24 @@ __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const ui
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
             const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.sigma);
+            const float xb = p[q].xf + k.phi;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                step<SCHEME>(k, p[q], z.z[j]);
-            wrap(p[q]);
+                step<SCHEME>(k, p[q], xb, z.z[j]);
+            end_block(p[q]);
         }
         ++blk;
     }
     n += nblk << 2;
-    // trailing partial block (no wrap: the block is finished by the next call)
+    // trailing partial block (its end is taken by the call that finishes the block)
     if (n < stop) {
         const uint32_t j1 = (uint32_t)(stop - n);
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
             const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.sigma);
+            const float xb = p[q].xf + k.phi;
             for (uint32_t j = 0; j < j1; ++j)
-                step<SCHEME>(k, p[q], pick(z, j));
+                step<SCHEME>(k, p[q], xb, pick(z, j));
         }
         n = stop;
     }
@@ -249,10 +283,15 @@ __device__ __forceinline__ double wave_sum(double x)
     return x;
 }
 
-// Histogram bin of x = cell + xf, decided in FP64: floor(n_bins * (x - floor x)), clamped.
-__device__ __forceinline__ int32_t hist_bin(int32_t cell, float xf, int32_t n_bins)
+// Position cell + xf + lx in FP64 (evaluated left to right).
+__device__ __forceinline__ double position64(int32_t cell, float xf, float lx)
 {
-    const double x = (double)cell + (double)xf;
+    return ((double)cell + (double)xf) + (double)lx;
+}
+
+// Histogram bin of a position, decided in FP64: floor(n_bins * (x - floor x)), clamped.
+__device__ __forceinline__ int32_t hist_bin(double x, int32_t n_bins)
+{
     const double frac = x - floor(x);
     if (!(frac >= 0.0))
         return 0;  // not reached for finite positions

@@ -7,16 +7,48 @@
 //   uint32 hist[n_bins]       counts of x mod 1 (integer atomics: order-free, hence deterministic)
 // Tiles do not depend on the launch shape, and abp_reduce adds them in a fixed order, so the
 // results are bit-identical for every tuning.
-#include "common.hpp"
+#include "reduce.hpp"
 
 namespace abp {
 
-struct FwdArgs {
+// Device view of an abp_state: cell, xf, v, e and the low parts lo[0:n] = lx, lo[n:2n] = lv,
+// lo[2n:3n] = le.
+struct StateView {
     int32_t *cell;
-    float *xf, *v, *e;
-    int32_t *scell;  // window snapshot (may be null when no window)
-    float *sxf;
+    float *xf, *v, *e, *lo;
     int64_t n;
+
+    __device__ __forceinline__ Particle load(int64_t i) const
+    {
+        Particle p;
+        p.cell = cell[i];
+        p.xf = xf[i];
+        p.v = v[i];
+        p.e = e[i];
+        p.lx = lo[i];
+        p.lv = lo[n + i];
+        p.le = lo[2 * n + i];
+        return p;
+    }
+    __device__ __forceinline__ void store(int64_t i, const Particle &p) const
+    {
+        cell[i] = p.cell;
+        xf[i] = p.xf;
+        v[i] = p.v;
+        e[i] = p.e;
+        lo[i] = p.lx;
+        lo[n + i] = p.lv;
+        lo[2 * n + i] = p.le;
+    }
+    __device__ __forceinline__ double x64(int64_t i) const
+    {
+        return position64(cell[i], xf[i], lo[i]);
+    }
+};
+
+struct FwdArgs {
+    StateView st;
+    StateView snap;  // window snapshot (whole state); unused pointers may be null
     uint32_t id0;
     int32_t n_bins;
     Coef k;
@@ -26,32 +58,9 @@ struct FwdArgs {
     uint32_t *hist;
 };
 
-inline size_t hist_offset(int64_t n) { return align_up((size_t)n_tiles(n) * 2 * sizeof(double), 256); }
-
-// Per-tile sums of the window displacement and the histogram update for the PPL particles held
-// by one lane. Lanes past the end contribute zero and count nothing.
-template <int PPL>
-__device__ __forceinline__ void reduce_tiles(const Particle (&p)[PPL], const int32_t (&sc)[PPL],
-                                             const float (&sx)[PPL], const bool (&live)[PPL],
-                                             int64_t first_tile, int64_t n, int lane,
-                                             int32_t n_bins, double *part, uint32_t *hist)
+inline size_t hist_offset(int64_t n)
 {
-#pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-        if ((first_tile + q) * 64 >= n)
-            break;  // wavefront-uniform: this tile lies past the last particle
-        double d = 0.0;
-        if (live[q])
-            d = (double)(p[q].cell - sc[q]) + ((double)p[q].xf - (double)sx[q]);
-        const double s1 = wave_sum(d);
-        const double s2 = wave_sum(d * d);
-        if (lane == 0) {
-            part[2 * (first_tile + q)] = s1;
-            part[2 * (first_tile + q) + 1] = s2;
-        }
-        if (n_bins > 0 && live[q])
-            atomicAdd(&hist[hist_bin(p[q].cell, p[q].xf, n_bins)], 1u);
-    }
+    return align_up((size_t)n_tiles(n) * 2 * sizeof(double), 256);
 }
 
 template <int SCHEME, int PPL, int UNROLL>
@@ -60,7 +69,8 @@ __global__ __launch_bounds__(256) void k_integrate(FwdArgs a)
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t base = wave * 64 * PPL;
-    if (base >= a.n)
+    const int64_t n = a.st.n;
+    if (base >= n)
         return;  // wavefront-uniform
 
     Particle p[PPL];
@@ -69,137 +79,80 @@ __global__ __launch_bounds__(256) void k_integrate(FwdArgs a)
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
         const int64_t i = base + 64 * q + lane;
-        live[q] = i < a.n;
+        live[q] = i < n;
         pid[q] = a.id0 + (uint32_t)i;
         if (live[q]) {
-            p[q].cell = a.cell[i];
-            p[q].xf = a.xf[i];
-            p[q].v = a.v[i];
-            p[q].e = a.e[i];
+            p[q] = a.st.load(i);
         } else {
             p[q].cell = 0;
-            p[q].xf = 0.0f;
-            p[q].v = 0.0f;
-            p[q].e = 0.0f;
+            p[q].xf = p[q].v = p[q].e = 0.0f;
+            p[q].lx = p[q].lv = p[q].le = 0.0f;
         }
     }
 
     const int64_t end = a.step0 + a.n_steps;
-    int64_t n = a.step0;
-    int32_t sc[PPL];
-    float sx[PPL];
+    int64_t step = a.step0;
+    double xs[PPL];
     const bool snap_here = a.win_begin >= a.step0 && a.win_begin <= end;
     if (snap_here) {
-        advance<SCHEME, PPL, UNROLL>(a.k, a.s, pid, p, n, a.win_begin);
+        advance<SCHEME, PPL, UNROLL>(a.k, a.s, pid, p, step, a.win_begin);
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-            sc[q] = p[q].cell;
-            sx[q] = p[q].xf;
-            if (live[q]) {
-                const int64_t i = base + 64 * q + lane;
-                a.scell[i] = sc[q];
-                a.sxf[i] = sx[q];
-            }
+            xs[q] = position64(p[q].cell, p[q].xf, p[q].lx);
+            if (live[q])
+                a.snap.store(base + 64 * q + lane, p[q]);
         }
     }
-    advance<SCHEME, PPL, UNROLL>(a.k, a.s, pid, p, n, end);
+    advance<SCHEME, PPL, UNROLL>(a.k, a.s, pid, p, step, end);
 
 #pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-        if (live[q]) {
-            const int64_t i = base + 64 * q + lane;
-            a.cell[i] = p[q].cell;
-            a.xf[i] = p[q].xf;
-            a.v[i] = p[q].v;
-            a.e[i] = p[q].e;
-        }
-    }
+    for (int q = 0; q < PPL; ++q)
+        if (live[q])
+            a.st.store(base + 64 * q + lane, p[q]);
 
     if (a.part) {
-        if (!snap_here) {
+        double xe[PPL];
 #pragma unroll
-            for (int q = 0; q < PPL; ++q) {
-                const int64_t i = base + 64 * q + lane;
-                sc[q] = live[q] ? a.scell[i] : 0;
-                sx[q] = live[q] ? a.sxf[i] : 0.0f;
-            }
+        for (int q = 0; q < PPL; ++q) {
+            xe[q] = position64(p[q].cell, p[q].xf, p[q].lx);
+            if (!snap_here)
+                xs[q] = live[q] ? a.snap.x64(base + 64 * q + lane) : 0.0;
         }
-        reduce_tiles<PPL>(p, sc, sx, live, base / 64, a.n, lane, a.n_bins, a.part, a.hist);
+        reduce_tiles<PPL>(xe, xs, live, base / 64, n, lane, a.n_bins, a.part, a.hist);
     }
 }
 
 // Reduction from two stored states (window start, window end); one particle per lane.
-__global__ __launch_bounds__(256) void k_reduce_state(const int32_t *scell, const float *sxf,
-                                                      const int32_t *ecell, const float *exf,
-                                                      int64_t n, int32_t n_bins, double *part,
-                                                      uint32_t *hist)
+__global__ __launch_bounds__(256) void k_reduce_state(StateView snap, StateView end,
+                                                      int32_t n_bins, double *part, uint32_t *hist)
 {
     const int lane = threadIdx.x & 63;
     const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64;
+    const int64_t n = end.n;
     if (base >= n)
         return;
     const int64_t i = base + lane;
-    Particle p[1];
-    int32_t sc[1];
-    float sx[1];
     bool live[1] = {i < n};
-    p[0].cell = live[0] ? ecell[i] : 0;
-    p[0].xf = live[0] ? exf[i] : 0.0f;
-    p[0].v = p[0].e = 0.0f;
-    sc[0] = live[0] ? scell[i] : 0;
-    sx[0] = live[0] ? sxf[i] : 0.0f;
-    reduce_tiles<1>(p, sc, sx, live, base / 64, n, lane, n_bins, part, hist);
+    double xe[1] = {live[0] ? end.x64(i) : 0.0};
+    double xs[1] = {live[0] ? snap.x64(i) : 0.0};
+    reduce_tiles<1>(xe, xs, live, base / 64, n, lane, n_bins, part, hist);
 }
 
-__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t count)
+// Fixed-order FP64 combine of the tile partials by one wavefront (the same routine finishes each
+// set of a batched sweep, so a set run alone and inside a sweep agree bit for bit).
+__global__ __launch_bounds__(64) void k_finalize(const double *part, int64_t ntiles,
+                                                 const uint32_t *hist32, int32_t n_bins, int64_t n,
+                                                 double window_time, double *out, uint64_t *hist64)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count)
-        p[i] = 0u;
-}
-
-// Fixed-order FP64 combine of the tile partials: thread t adds tiles t, t + 1024, ... in order,
-// then a fixed LDS tree. Also widens the u32 histogram to u64.
-__global__ __launch_bounds__(1024) void k_finalize(const double *part, int64_t ntiles,
-                                                   const uint32_t *hist32, int32_t n_bins,
-                                                   int64_t n, double window_time, double *out,
-                                                   uint64_t *hist64)
-{
-    __shared__ double s1s[1024];
-    __shared__ double s2s[1024];
-    const int t = threadIdx.x;
-    double s1 = 0.0, s2 = 0.0;
-    for (int64_t i = t; i < ntiles; i += 1024) {
-        s1 += part[2 * i];
-        s2 += part[2 * i + 1];
-    }
-    s1s[t] = s1;
-    s2s[t] = s2;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (t < w) {
-            s1s[t] += s1s[t + w];
-            s2s[t] += s2s[t + w];
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        const double S1 = s1s[0], S2 = s2s[0];
-        const double mean_d = S1 / (double)n;
-        double var_d = n > 1 ? (S2 - S1 * mean_d) / (double)(n - 1) : 0.0;
-        if (var_d < 0.0)
-            var_d = 0.0;
-        out[0] = mean_d / window_time;
-        out[1] = sqrt(var_d / (double)n) / window_time;
-    }
-    for (int b = t; b < n_bins; b += 1024)
+    finalize_set(part, ntiles, n, window_time, out);
+    for (int b = threadIdx.x; b < n_bins; b += 64)
         hist64[b] = hist32[b];
 }
 
 template <int SCHEME, int PPL, int UNROLL>
 static void launch_integrate(const FwdArgs &a, int block, hipStream_t st)
 {
-    const int64_t waves = (a.n + 64 * PPL - 1) / (64 * PPL);
+    const int64_t waves = (a.st.n + 64 * PPL - 1) / (64 * PPL);
     const int64_t threads = waves * 64;
     const unsigned grid = (unsigned)((threads + block - 1) / block);
     hipLaunchKernelGGL((k_integrate<SCHEME, PPL, UNROLL>), dim3(grid), dim3(block), 0, st, a);
@@ -226,8 +179,7 @@ constexpr Shape kDefaultForward = {256, 1, 1, 8};
 static void zero_hist(uint32_t *hist, int32_t n_bins, hipStream_t st)
 {
     if (n_bins > 0)
-        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n_bins + 255) / 256)), dim3(256), 0, st,
-                           hist, (int64_t)n_bins);
+        fill_u32(hist, n_bins, st);
 }
 
 }  // namespace abp
@@ -239,6 +191,18 @@ extern "C" size_t abp_reduce_workspace_bytes(int64_t n, int32_t n_bins)
     if (n < 1 || n > kMaxParticles || !bins_ok(n_bins))
         return 0;
     return hist_offset(n) + align_up((size_t)n_bins * sizeof(uint32_t), 256);
+}
+
+static StateView view(const abp_state *s)
+{
+    StateView v;
+    v.cell = s->d_cell;
+    v.xf = s->d_xf;
+    v.v = s->d_v;
+    v.e = s->d_e;
+    v.lo = s->d_lo;
+    v.n = s->n;
+    return v;
 }
 
 extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const abp_state *s,
@@ -256,9 +220,7 @@ extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const
     const bool reduce = d_ws != nullptr;
     if (reduce && (r->win_begin < 0 || r->win_begin > end))
         return ABP_E_ARG;  // a reduction needs a window that is open by the end of the call
-    if ((snap_write || reduce) &&
-        (!snap || !snap->d_cell || !snap->d_xf || !aligned(snap->d_cell, 4) ||
-         !aligned(snap->d_xf, 4) || snap->n != s->n))
+    if ((snap_write || reduce) && (!state_ok(snap) || snap->n != s->n))
         return ABP_E_ARG;
     if (reduce && (!bins_ok(n_bins) || !aligned(d_ws, 256)))
         return ABP_E_ARG;
@@ -271,13 +233,9 @@ extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const
         return st;
 
     FwdArgs a{};
-    a.cell = s->d_cell;
-    a.xf = s->d_xf;
-    a.v = s->d_v;
-    a.e = s->d_e;
-    a.scell = (snap_write || reduce) ? snap->d_cell : nullptr;
-    a.sxf = (snap_write || reduce) ? snap->d_xf : nullptr;
-    a.n = s->n;
+    a.st = view(s);
+    if (snap_write || reduce)
+        a.snap = view(snap);
     a.id0 = s->id0;
     a.n_bins = reduce ? n_bins : 0;
     a.k = make_coef(*p, r->dt);
@@ -302,10 +260,8 @@ extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const
 extern "C" abp_status abp_reduce_state(const abp_state *snap, const abp_state *end,
                                        int32_t n_bins, void *d_ws, size_t ws_bytes, void *stream)
 {
-    if (!snap || !end || !snap->d_cell || !snap->d_xf || !end->d_cell || !end->d_xf ||
-        !aligned(snap->d_cell, 4) || !aligned(snap->d_xf, 4) || !aligned(end->d_cell, 4) ||
-        !aligned(end->d_xf, 4) || snap->n != end->n || end->n < 1 || end->n > kMaxParticles ||
-        !bins_ok(n_bins) || !d_ws || !aligned(d_ws, 256))
+    if (!state_ok(snap) || !state_ok(end) || snap->n != end->n || !bins_ok(n_bins) || !d_ws ||
+        !aligned(d_ws, 256))
         return ABP_E_ARG;
     if (ws_bytes < abp_reduce_workspace_bytes(end->n, n_bins))
         return ABP_E_WORKSPACE;
@@ -317,8 +273,8 @@ extern "C" abp_status abp_reduce_state(const abp_state *snap, const abp_state *e
                                                   hist_offset(end->n));
     zero_hist(hist, n_bins, st);
     const unsigned grid = (unsigned)((n_tiles(end->n) * 64 + 255) / 256);
-    hipLaunchKernelGGL(k_reduce_state, dim3(grid), dim3(256), 0, st, snap->d_cell, snap->d_xf,
-                       end->d_cell, end->d_xf, end->n, n_bins, part, hist);
+    hipLaunchKernelGGL(k_reduce_state, dim3(grid), dim3(256), 0, st, view(snap), view(end), n_bins,
+                       part, hist);
     return launch_status();
 }
 
@@ -334,7 +290,7 @@ extern "C" abp_status abp_reduce(const void *d_ws, int64_t n, int32_t n_bins, do
     const double *part = reinterpret_cast<const double *>(d_ws);
     const uint32_t *hist = reinterpret_cast<const uint32_t *>(
         reinterpret_cast<const char *>(d_ws) + hist_offset(n));
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, as_stream(stream), part, n_tiles(n),
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, as_stream(stream), part, n_tiles(n),
                        hist, n_bins, n, window_time, d_out, d_hist);
     return launch_status();
 }

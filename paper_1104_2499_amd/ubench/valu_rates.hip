@@ -1,9 +1,10 @@
 // valu_rates.hip -- issue cost of the VALU instruction classes the integrator uses, on gfx950.
 //
-// Each kernel runs CHAINS independent dependency chains per lane of one instruction class for
-// ITERS iterations, on a grid that fills every SIMD with 8 waves. The time per instruction,
-// divided by the time per v_fma_f32 measured the same way, is that class's cost in full-rate
-// VALU issue slots. Prints "name: ns_per_wave_instr_per_simd slots" lines.
+// Each kernel runs CHAINS independent dependency chains per lane of one instruction (or of a
+// fixed pair of instructions) for ITERS iterations, on a grid of 256-thread blocks giving W waves
+// per SIMD. The time per wave-instruction per SIMD, divided by that of v_fma_f32 at 8 waves per
+// SIMD, is the cost of the class in FMA issue slots. Pairs show which classes overlap.
+// Output: one line per measurement, then "key: value" summary lines.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -22,64 +23,88 @@
         }                                                                          \
     } while (0)
 
+enum Op {
+    FMA, ADD, MUL, COS, LOG, SQRT, MAD64, MULHI, MULLO, BITOP3, ADDU, CVT, FMA64,
+    MIX_FMA_COS, MIX_FMA_MAD64, MIX_FMA_BITOP3, MIX_COS_MAD64, N_OPS
+};
+static const char *kNames[N_OPS] = {
+    "v_fma_f32", "v_add_f32", "v_mul_f32", "v_cos_f32", "v_log_f32", "v_sqrt_f32",
+    "mad_u64+mov", "v_mul_hi_u32", "v_mul_lo_u32", "v_bitop3_b32", "v_add_u32",
+    "v_cvt_f32_u32", "v_fma_f64", "fma+cos", "fma+mad64+mov", "fma+bitop3", "cos+mad64+mov"};
+// v_mad_u64_u32 chains carry one v_mov_b32 each (the zero high word of the addend)
+static const int kInstr[N_OPS] = {1, 1, 1, 1, 1, 1, 2, 1, 1, 1, 1, 1, 1, 2, 3, 2, 3};
+
+__device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c)
+{
+    return (uint64_t)a * (uint64_t)b + c;  // selects v_mad_u64_u32
+}
+
 template <int OP>
 __global__ __launch_bounds__(256) void k_rate(float *out, float seedf, uint32_t seedu)
 {
     float f[CHAINS];
     uint32_t u[CHAINS];
+    uint64_t w[CHAINS];
+    double d[CHAINS];
+    const float g = seedf * 0.5f + (float)(threadIdx.x & 1), h = seedf * 0.25f;
+    const uint32_t m = seedu | 1u;
     for (int c = 0; c < CHAINS; ++c) {
         f[c] = seedf + 0.01f * (float)(threadIdx.x + c);
         u[c] = seedu + threadIdx.x * 7u + (uint32_t)c;
+        w[c] = u[c];
+        d[c] = f[c];
     }
     for (int it = 0; it < ITERS; ++it) {
 #pragma unroll
         for (int c = 0; c < CHAINS; ++c) {
-            if constexpr (OP == 0) {  // v_fma_f32
-                f[c] = fmaf(f[c], 0.999f, 0.001f);
-            } else if constexpr (OP == 1) {  // v_cos_f32
+            if constexpr (OP == FMA) f[c] = fmaf(f[c], g, h);
+            else if constexpr (OP == ADD) f[c] = f[c] + g;
+            else if constexpr (OP == MUL) f[c] = f[c] * g;
+            else if constexpr (OP == COS) f[c] = __builtin_amdgcn_cosf(f[c]);
+            else if constexpr (OP == LOG) f[c] = __builtin_amdgcn_logf(f[c]);
+            else if constexpr (OP == SQRT) f[c] = __builtin_amdgcn_sqrtf(f[c]);
+            else if constexpr (OP == MAD64) w[c] = mad64((uint32_t)w[c], m, w[c] >> 32);
+            else if constexpr (OP == MULHI) u[c] = __umulhi(u[c], m);
+            else if constexpr (OP == MULLO) u[c] = u[c] * m;
+            else if constexpr (OP == BITOP3)
+                u[c] = __builtin_amdgcn_bitop3_b32(u[c], m, (uint32_t)c, 0x96);
+            else if constexpr (OP == ADDU) u[c] = u[c] + m;
+            else if constexpr (OP == CVT) f[c] = (float)__float_as_uint(f[c]);
+            else if constexpr (OP == FMA64) d[c] = fma(d[c], (double)g, (double)h);
+            if constexpr (OP == MIX_FMA_COS) {
+                // independent FMA and cos chains, interleaved
+                f[c] = fmaf(f[c], g, h);
+                u[c] = __float_as_uint(__builtin_amdgcn_cosf(__uint_as_float(u[c])));
+            } else if constexpr (OP == MIX_FMA_MAD64) {
+                f[c] = fmaf(f[c], g, h);
+                w[c] = mad64((uint32_t)w[c], m, w[c] >> 32);
+            } else if constexpr (OP == MIX_FMA_BITOP3) {
+                f[c] = fmaf(f[c], g, h);
+                u[c] = __builtin_amdgcn_bitop3_b32(u[c], m, (uint32_t)c, 0x96);
+            } else if constexpr (OP == MIX_COS_MAD64) {
                 f[c] = __builtin_amdgcn_cosf(f[c]);
-            } else if constexpr (OP == 2) {  // v_sin_f32
-                f[c] = __builtin_amdgcn_sinf(f[c]);
-            } else if constexpr (OP == 3) {  // v_log_f32
-                f[c] = __builtin_amdgcn_logf(f[c]);
-            } else if constexpr (OP == 4) {  // v_sqrt_f32
-                f[c] = __builtin_amdgcn_sqrtf(f[c]);
-            } else if constexpr (OP == 5) {  // v_mad_u64_u32 (both halves kept)
-                uint64_t r;
-                asm volatile("v_mad_u64_u32 %0, vcc, %1, %2, 0" : "=v"(r) : "v"(u[c]),
-                             "v"(0xD2511F53u) : "vcc");
-                u[c] = (uint32_t)r + (uint32_t)(r >> 32);
-            } else if constexpr (OP == 6) {  // v_mul_hi_u32
-                u[c] = __umulhi(u[c], 0xD2511F53u) + 1u;
-            } else if constexpr (OP == 7) {  // v_bitop3_b32
-                u[c] = __builtin_amdgcn_bitop3_b32(u[c], 0x9E3779B9u, (uint32_t)c, 0x96);
-            } else if constexpr (OP == 8) {  // v_cvt_f32_u32
-                f[c] = (float)(__float_as_uint(f[c]) >> 8);
+                w[c] = mad64((uint32_t)w[c], m, w[c] >> 32);
             }
         }
     }
     float acc = 0.0f;
     for (int c = 0; c < CHAINS; ++c)
-        acc += f[c] + (float)u[c];
+        acc += f[c] + (float)u[c] + (float)(uint32_t)w[c] + (float)d[c];
     out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
 }
 
-// instructions per chain-iteration beyond the measured one (loop bookkeeping is SALU)
-static const char *kNames[] = {"fma_f32", "cos_f32", "sin_f32", "log_f32", "sqrt_f32",
-                               "mad_u64_u32+add", "mul_hi_u32+add", "bitop3_b32", "lshr+cvt_f32"};
-static const double kInstr[] = {1, 1, 1, 1, 1, 2, 2, 1, 2};
+typedef void (*Kern)(float *, float, uint32_t);
 
-template <int OP>
-static double run(float *d_out, int grid, int block)
+static double time_kernel(Kern k, float *d_out, int grid)
 {
     hipEvent_t a, b;
     CHECK(hipEventCreate(&a));
     CHECK(hipEventCreate(&b));
-    hipLaunchKernelGGL(k_rate<OP>, dim3(grid), dim3(block), 0, 0, d_out, 0.5f, 12345u);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, 0, d_out, 0.5f, 12345u);
     CHECK(hipEventRecord(a));
     const int reps = 5;
     for (int r = 0; r < reps; ++r)
-        hipLaunchKernelGGL(k_rate<OP>, dim3(grid), dim3(block), 0, 0, d_out, 0.5f, 12345u);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, 0, d_out, 0.5f, 12345u);
     CHECK(hipEventRecord(b));
     CHECK(hipEventSynchronize(b));
     float ms = 0;
@@ -90,45 +115,48 @@ static double run(float *d_out, int grid, int block)
     return ms / reps;
 }
 
+template <int... OPS>
+struct Table {
+    static constexpr Kern k[sizeof...(OPS)] = {k_rate<OPS>...};
+};
+
 int main()
 {
     hipDeviceProp_t prop;
     CHECK(hipGetDeviceProperties(&prop, 0));
     const int cus = prop.multiProcessorCount;
-    const int block = 256, grid = cus * 8;  // 8 waves per SIMD
     float *d_out = nullptr;
-    CHECK(hipMalloc(&d_out, sizeof(float) * (size_t)grid * block));
-    double ms[9];
-    ms[0] = run<0>(d_out, grid, block);
-    ms[1] = run<1>(d_out, grid, block);
-    ms[2] = run<2>(d_out, grid, block);
-    ms[3] = run<3>(d_out, grid, block);
-    ms[4] = run<4>(d_out, grid, block);
-    ms[5] = run<5>(d_out, grid, block);
-    ms[6] = run<6>(d_out, grid, block);
-    ms[7] = run<7>(d_out, grid, block);
-    ms[8] = run<8>(d_out, grid, block);
-    const double waves_per_simd = (double)grid * block / 64.0 / (cus * 4.0);
+    CHECK(hipMalloc(&d_out, sizeof(float) * (size_t)cus * 8 * 256));
+    using T = Table<FMA, ADD, MUL, COS, LOG, SQRT, MAD64, MULHI, MULLO, BITOP3, ADDU, CVT, FMA64,
+                    MIX_FMA_COS, MIX_FMA_MAD64, MIX_FMA_BITOP3, MIX_COS_MAD64>;
+    std::printf("# device: %s, %d CUs, max clock %d kHz; %d chains x %d iterations per lane\n",
+                prop.gcnArchName, cus, prop.clockRate, CHAINS, ITERS);
     const double instr_per_wave = (double)ITERS * CHAINS;
-    std::printf("# device: %s, %d CUs, clock %d kHz\n", prop.gcnArchName, cus, prop.clockRate);
-    std::printf("# grid %d x %d threads (%.0f waves/SIMD), %d chains x %d iterations per lane\n",
-                grid, block, waves_per_simd, CHAINS, ITERS);
-    const double ns_fma = ms[0] * 1e6 / (waves_per_simd * instr_per_wave * kInstr[0]);
-    for (int i = 0; i < 9; ++i) {
-        const double ns = ms[i] * 1e6 / (waves_per_simd * instr_per_wave * kInstr[i]);
-        std::printf("%-16s %8.3f ms  %7.4f ns/wave-instr/SIMD  %5.2f slots (avg over %g instr)\n",
-                    kNames[i], ms[i], ns, ns / ns_fma, kInstr[i]);
+    double ns8[N_OPS];
+    for (int wps : {1, 2, 4, 8}) {
+        const int grid = cus * wps;  // 4 waves per block: wps waves per SIMD
+        for (int op = 0; op < N_OPS; ++op) {
+            if (wps != 8 && op != FMA && op != COS && op != MAD64)
+                continue;
+            const double ms = time_kernel(T::k[op], d_out, grid);
+            const double ns = ms * 1e6 / (wps * instr_per_wave * kInstr[op]);
+            if (wps == 8)
+                ns8[op] = ns;
+            std::printf("%-14s waves/SIMD %d  %8.4f ms  %7.4f ns per wave-instr per SIMD\n",
+                        kNames[op], wps, ms, ns);
+        }
     }
-    // cost of the class itself, with the companion full-rate op removed
-    const double slot_ns = ns_fma;
-    auto slots = [&](int i) { return ms[i] * 1e6 / (waves_per_simd * instr_per_wave) / slot_ns; };
-    std::printf("fma_slot_ns: %.4f\n", slot_ns);
-    std::printf("implied_clock_ghz: %.3f\n", 4.0 / slot_ns);
-    const double trans = (slots(1) + slots(2) + slots(3) + slots(4)) / 4.0;
-    std::printf("trans_slots: %.3f\n", trans);
-    std::printf("mad64_slots: %.3f\n", slots(5) - 1.0);
-    std::printf("mul_hi_slots: %.3f\n", slots(6) - 1.0);
-    std::printf("bitop3_slots: %.3f\n", slots(7));
+    const double fma = ns8[FMA];
+    std::printf("fma_ns: %.4f\n", fma);
+    std::printf("fma_cycles_at_max_clock: %.3f\n", fma * prop.clockRate * 1e-6);
+    std::printf("trans_slots: %.3f\n", (ns8[COS] + ns8[LOG] + ns8[SQRT]) / 3.0 / fma);
+    std::printf("mad64_slots: %.3f\n", (2.0 * ns8[MAD64] - ns8[ADDU]) / fma);
+    std::printf("mul_hi_slots: %.3f\n", ns8[MULHI] / fma);
+    std::printf("bitop3_slots: %.3f\n", ns8[BITOP3] / fma);
+    std::printf("int_slots: %.3f\n", (ns8[ADDU] + ns8[CVT]) / 2.0 / fma);
+    std::printf("fp32_addmul_slots: %.3f\n", (ns8[ADD] + ns8[MUL]) / 2.0 / fma);
+    std::printf("pair_fma_cos_slots_per_instr: %.3f\n", ns8[MIX_FMA_COS] / fma);
+    std::printf("pair_fma_mad64_slots_per_instr: %.3f\n", ns8[MIX_FMA_MAD64] / fma);
     CHECK(hipFree(d_out));
     return 0;
 }

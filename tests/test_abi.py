@@ -54,7 +54,7 @@ def test_workspace_queries(lib):
 def _state(n=64, ptr=0x1000, id0=0):
     from paper_1104_2499_amd import _lib
 
-    return _lib.AbpState(ptr, ptr, ptr, ptr, n, id0, 0)
+    return _lib.AbpState(ptr, ptr, ptr, ptr, ptr, n, id0, 0)
 
 
 def test_integrate_rejects_bad_arguments_without_a_device(lib):

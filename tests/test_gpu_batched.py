@@ -1,0 +1,110 @@
+"""GPU checks of the persistent batched sweep: every set equals the same set run alone (bit for
+bit, for every tuning), sets match the FP64 oracle, and the full 4096-set sweep is consistent."""
+import numpy as np
+import pytest
+import torch
+
+from conftest import mixed_err  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("U0", "a", "phi", "gamma0", "F0", "d2", "q", "c", "D")
+
+
+def _small_sweep():
+    rng = np.random.default_rng(5)
+    n_sets = 12
+    from paper_1104_2499_amd.workloads import sweep_table
+
+    table, _, _ = sweep_table(n_sets, seed=5)
+    n_traj = np.array([1, 63, 64, 65, 200, 1000, 129, 7, 513, 64, 2, 300], dtype=np.int32)
+    n_steps = np.array([1, 3, 4, 5, 401, 1000, 998, 17, 640, 2, 1203, 77], dtype=np.int64)
+    window = np.maximum(1, n_steps // np.array([1, 2, 3, 2, 2, 5, 2, 3, 4, 1, 2, 7]))
+    return table, n_traj, n_steps, window.astype(np.int64), rng
+
+
+def _alone(k, table, n_traj, n_steps, window, scheme, seed, bins):
+    from paper_1104_2499_amd import api
+
+    params = {key: float(table[k, i]) for i, key in enumerate(KEYS)}
+    return api.run(params, n=int(n_traj[k]), steps=int(n_steps[k]), window=int(window[k]),
+                   scheme=scheme, seed=seed, bins=bins, set_id=k)
+
+
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_each_set_equals_its_single_run_for_every_tuning(gpu, scheme):
+    from paper_1104_2499_amd import api
+
+    table, n_traj, n_steps, window, _ = _small_sweep()
+    bins, seed = 32, 11
+    alone = [_alone(k, table, n_traj, n_steps, window, scheme, seed, bins)
+             for k in range(len(n_traj))]
+    for block in (64, 256):
+        for ppl in (1, 2):
+            for unroll in (1, 2):
+                for wps in (1, 8):
+                    r = api.sweep(table, n_traj, n_steps, window, scheme=scheme, seed=seed,
+                                  bins=bins, tune=dict(block=block, ppl=ppl, unroll=unroll,
+                                                       waves_per_simd=wps))
+                    for k, a in enumerate(alone):
+                        assert r.mean_v[k] == a.mean_v, (k, block, ppl, unroll, wps)
+                        assert r.stderr[k] == a.stderr
+                        assert torch.equal(r.hist[k], a.hist)
+
+
+def test_sets_match_oracle(gpu, orc):
+    from paper_1104_2499_amd import api
+
+    table, n_traj, n_steps, window, _ = _small_sweep()
+    r = api.sweep(table, n_traj, n_steps, window, scheme="em", seed=11, bins=64)
+    for k in range(len(n_traj)):
+        params = {key: float(table[k, i]) for i, key in enumerate(KEYS)}
+        n = int(n_traj[k])
+        x0, v0, e0 = orc.init_state(n, 11, k)
+        x, v, e, xs, _ = orc.integrate(params, x0, v0, e0, int(n_steps[k]), seed=11, set_id=k,
+                                       win_begin=int(n_steps[k] - window[k]))
+        mean, se, hist = orc.reduce(xs, x, float(window[k]) * 1e-3, 64)
+        assert abs(r.mean_v[k] - mean) <= 1e-5 * max(1.0, abs(mean)), k
+        assert int(r.hist[k].sum()) == n
+
+
+def test_full_sweep_4096_sets(gpu, orc):
+    """The 4096-set ratchet sweep (D log-uniform, U0, a, d2 uniform; 64..4096 trajectories and
+    2e4..2e5 steps per set) in one launch: sampled sets are bit-identical to their single runs,
+    every histogram holds its set's trajectories, and a short set agrees with the oracle."""
+    from paper_1104_2499_amd import api
+    from paper_1104_2499_amd.workloads import WORKLOADS, sweep_table
+
+    wl = WORKLOADS["sweep-4096"]
+    table, n_traj, n_steps = sweep_table(wl["n_sets"], seed=wl["seed"])
+    r = api.sweep(table, n_traj, n_steps, scheme="em", seed=wl["seed"], bins=wl["bins"])
+    np.testing.assert_array_equal(r.hist.sum(dim=1).cpu().numpy(), n_traj)
+    assert np.all(np.isfinite(r.mean_v)) and np.all(r.stderr > 0)
+    order = np.argsort(n_traj.astype(np.int64) * n_steps)
+    for k in (int(order[0]), int(order[1]), 0, wl["n_sets"] - 1):
+        a = _alone(k, table, n_traj, n_steps, n_steps // 2, "em", wl["seed"], wl["bins"])
+        assert r.mean_v[k] == a.mean_v and r.stderr[k] == a.stderr
+        assert torch.equal(r.hist[k], a.hist)
+    k = int(order[0])
+    params = {key: float(table[k, i]) for i, key in enumerate(KEYS)}
+    n, S = int(n_traj[k]), int(n_steps[k])
+    x0, v0, e0 = orc.init_state(n, wl["seed"], k)
+    x, v, e, xs, _ = orc.integrate(params, x0, v0, e0, S, seed=wl["seed"], set_id=k,
+                                   win_begin=S - S // 2)
+    mean, se, _ = orc.reduce(xs, x, (S // 2) * 1e-3, wl["bins"])
+    assert abs(r.mean_v[k] - mean) <= 4 * np.hypot(r.stderr[k], se)
+
+
+def test_batched_rejects_bad_arguments(gpu):
+    from paper_1104_2499_amd import api
+
+    table, n_traj, n_steps, window, _ = _small_sweep()
+    bad = n_traj.copy()
+    bad[3] = 0
+    with pytest.raises(ValueError):
+        api.batched_workspace(bad, 32)
+    with pytest.raises(api.AbpError, match="ABP_E_ARG"):
+        api.sweep(table, n_traj, n_steps, window * 0, bins=32)
+    ws = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(api.AbpError, match="ABP_E_WORKSPACE"):
+        api.sweep(table, n_traj, n_steps, window, bins=32, ws=ws)

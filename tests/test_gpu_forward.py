@@ -70,8 +70,7 @@ def _run_pair(orc, params, n, steps, scheme, seed=42, window=None, dt=1e-3, bins
 
 
 def _gpu_xve(res):
-    return (_np(res.state.x64()), _np(res.state.v).astype(np.float64),
-            _np(res.state.e).astype(np.float64))
+    return (_np(res.state.x64()), _np(res.state.v64()), _np(res.state.e64()))
 
 
 @pytest.mark.parametrize("scheme", ["em", "heun"])
@@ -149,8 +148,7 @@ def test_chunked_equals_unchunked_bitwise(gpu, scheme):
         api.integrate(s, k, BASE, scheme=scheme, seed=9, step0=step0, win_begin=501, snap=snap,
                       ws=ws if last else None, n_bins=bins)
     out, hist = api.reduce(ws, n, bins, 502e-3)
-    for a_, b_ in ((one.state.cell, s.cell), (one.state.xf, s.xf), (one.state.v, s.v),
-                   (one.state.e, s.e), (one.snap.xf, snap.xf), (one.snap.cell, snap.cell)):
+    for a_, b_ in zip(one.state.tensors() + one.snap.tensors(), s.tensors() + snap.tensors()):
         assert torch.equal(a_, b_)
     assert float(out[0].cpu()) == one.mean_v and float(out[1].cpu()) == one.stderr
     assert torch.equal(hist, one.hist)
@@ -165,8 +163,8 @@ def test_every_tuning_gives_identical_results(gpu):
             for unroll in (1, 2):
                 r = api.run(BASE, n=5000, steps=403, window=201, scheme="heun", seed=3, bins=128,
                             tune=dict(block=block, ppl=ppl, unroll=unroll))
-                got = (_np(r.state.cell), _np(r.state.xf), _np(r.state.v), _np(r.state.e),
-                       r.mean_v, r.stderr, _np(r.hist))
+                got = tuple(_np(t) for t in r.state.tensors()) + (r.mean_v, r.stderr,
+                                                                   _np(r.hist))
                 if ref is None:
                     ref = got
                     continue
@@ -185,18 +183,25 @@ def test_reduce_state_histogram_bit_exact(gpu, orc):
     xf[:256] = edges                                        # exactly on bin edges
     xf[256:512] = np.nextafter(edges, np.float32(-1))       # just below them
     xf[512:520] = [0.0, -0.0, 1.0, -1e-30, 1.0 - 2**-24, -0.5, 1.5, -2**-26]
+    lx = (rng.standard_normal(n) * 1e-8).astype(np.float32)
+    lx[:512] = 0.0
     scell = rng.integers(-10, 10, n).astype(np.int32)
     sxf = rng.random(n).astype(np.float32)
-    end = api.State(torch.from_numpy(cell).cuda(), torch.from_numpy(xf).cuda(),
-                    torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"))
-    snap = api.State(torch.from_numpy(scell).cuda(), torch.from_numpy(sxf).cuda(),
-                     torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"))
+    slx = (rng.standard_normal(n) * 1e-8).astype(np.float32)
+    z = torch.zeros(n, device="cuda")
+
+    def state(c, x, l):
+        lo = torch.zeros((3, n), device="cuda")
+        lo[0] = torch.from_numpy(l).cuda()
+        return api.State(torch.from_numpy(c).cuda(), torch.from_numpy(x).cuda(), z, z, lo)
+
+    end, snap = state(cell, xf, lx), state(scell, sxf, slx)
     for bins in (256, 4096, 1):
         ws = api.reduce_workspace(n, bins)
         api.reduce_state(snap, end, bins, ws)
         out, hist = api.reduce(ws, n, bins, 3.5)
-        xe = cell.astype(np.float64) + xf.astype(np.float64)
-        xs = scell.astype(np.float64) + sxf.astype(np.float64)
+        xe = (cell.astype(np.float64) + xf.astype(np.float64)) + lx.astype(np.float64)
+        xs = (scell.astype(np.float64) + sxf.astype(np.float64)) + slx.astype(np.float64)
         mean, se, h = orc.reduce(xs, xe, 3.5, bins)
         np.testing.assert_array_equal(_np(hist).astype(np.uint64), h)
         assert float(out[0].cpu()) == pytest.approx(mean, rel=1e-12)
@@ -228,7 +233,7 @@ def test_zero_steps_and_partial_blocks(gpu, orc):
     api.integrate(s, 2, BASE, step0=5, seed=2)
     x0, v0, e0 = orc.init_state(n, 2)
     x, v, e, _, _ = orc.integrate(BASE, x0, v0, e0, 2, step0=5, seed=2)
-    err = mixed_err((_np(s.x64()), _np(s.v), _np(s.e)), (x, v, e))
+    err = mixed_err((_np(s.x64()), _np(s.v64()), _np(s.e64())), (x, v, e))
     assert err.max() <= 1e-6
 
 
@@ -256,7 +261,7 @@ def test_full_size_heun_sampled(gpu, orc):
     x0, v0, e0 = orc.init_state(ids.size, 7, ids=ids)
     x, v, e, _, _ = orc.integrate(BASE, x0, v0, e0, 1000, scheme=1, seed=7, ids=ids)
     idx = torch.from_numpy(ids.astype(np.int64)).cuda()
-    g = (_np(res.state.x64()[idx]), _np(res.state.v[idx]), _np(res.state.e[idx]))
+    g = (_np(res.state.x64()[idx]), _np(res.state.v64()[idx]), _np(res.state.e64()[idx]))
     err = mixed_err(g, (x, v, e))
     assert err.max() <= 1e-3 and np.median(err) <= 1e-5
     assert int(_np(res.hist).sum()) == n
