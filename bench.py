@@ -22,47 +22,37 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD16 at 2.4 GHz = 256 * 64 lanes * 2.4e9 full-rate VALU lane-slots/s.
-VALU_LANE_SLOTS_PER_S = 256 * 64 * 2.4e9
+# MI355X figures: 256 CUs x 4 SIMDs, 2.4 GHz peak engine clock, FP32 vector peak 157.3 TFLOP/s.
+N_SIMD = 256 * 4
+CLOCK_HZ = 2.4e9
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# Issue rate of one wave64 VALU instruction per SIMD every 4 cycles (the rate at which the hot loop
+# is measured to run: SQ_INSTS_VALU per second per SIMD = CLOCK_HZ / 4).
+VALU_LANE_INSTR_PER_S = N_SIMD * 64 * CLOCK_HZ / 4
 
-# VALU cost of one particle-step of the hot loop, counted from the gfx950 ISA of
-# k_integrate<HEUN, 1, 1> (one Philox block = 4 steps per loop trip) and weighted by the issue cost
-# of each instruction class measured on the device (profiles/valu_issue_rates.txt):
-#   full-rate FP32/INT ops per 4 steps, transcendentals per 4 steps, v_mad_u64_u32 per 4 steps.
-ISA_HEUN = dict(full=156, trans=16, mad64=16)
-ISA_EM = dict(full=96, trans=12, mad64=16)
-# FP32 arithmetic of the method per particle-step (FMA = 2), transcendentals counted as 1 each:
-# Heun 2 drift evaluations (14 each) + predictor 7 + corrector 10 + Box-Muller share 3 + 4 trans.
-FLOP_PER_STEP = dict(heun=49 + 4, em=25 + 3)
+# Algorithmic FP32 FLOPs of the method per particle-step (FMA = 2): drift 14 (phase add, 2 FMAs for
+# F0 - U', 2 for f_v, mul + 2 FMAs for f_e), EM update 7, Heun predictor 7 + corrector 10 + a second
+# drift, and half a Box-Muller pair (5 per pair). Transcendentals are counted separately.
+FLOP_PER_STEP = dict(em=24, heun=48)
+TRANS_PER_STEP = dict(em=3, heun=4)
+# VALU instructions per particle-step in the hot loop of k_integrate<scheme, 1, 1> (gfx950 ISA,
+# one Philox block = 4 steps per loop trip: EM 133, Heun 193; SQ_INSTS_VALU of a profiled run
+# agrees to 0.02%).
+VALU_INSTR_PER_STEP = dict(em=133 / 4, heun=193 / 4)
+# Issue time of v_cos/v_sin/v_log/v_sqrt_f32 per wave64 instruction per SIMD, measured by
+# ubench/valu_rates.hip (profiles/valu_issue_rates.txt).
+TRANS_NS_PER_WAVE_INSTR = 3.43
 
 
-def issue_cost(counts: dict, rates: dict) -> float:
-    """Lane-slots per particle-step (full-rate op = 1 slot)."""
-    return (counts["full"] + counts["trans"] * rates["trans"] + counts["mad64"] * rates["mad64"]) / 4.0
-
-
-def load_rates() -> dict:
-    """Issue cost (in full-rate slots) of a transcendental and of v_mad_u64_u32 on gfx950, as
-    measured by the committed microbenchmark summary; defaults to the CDNA quarter rate."""
-    rates = dict(trans=4.0, mad64=4.0, source="assumed quarter rate")
-    path = os.path.join(ROOT, "profiles", "valu_issue_rates.txt")
-    if os.path.exists(path):
-        for line in open(path):
-            if line.startswith("trans_slots:"):
-                rates["trans"] = float(line.split(":")[1])
-            elif line.startswith("mad64_slots:"):
-                rates["mad64"] = float(line.split(":")[1])
-        rates["source"] = "profiles/valu_issue_rates.txt"
-    return rates
+KERNEL_SOURCES = ("common.hpp", "device.hpp", "reduce.hpp", "forward.hip")
 
 
 def source_hash() -> str:
+    """Hash of the sources the single-set integrator kernel is built from."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1104_2499_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -116,6 +106,98 @@ def cpu_baseline(wl: dict, params: dict, seconds_budget: float = 15.0) -> dict:
                       f"{dt_s:.1f} s"}
 
 
+def sweep_bench(reps: int = 2) -> dict:
+    """The 4096-set ratchet sweep in one persistent launch, and the single-set throughput of the
+    same scheme (2^20 particles of the base parameters) for comparison."""
+    import numpy as np
+    import torch
+
+    from paper_1104_2499_amd import api
+    from paper_1104_2499_amd.workloads import BASE_PARAMS, WORKLOADS, sweep_table
+
+    wl = WORKLOADS["sweep-4096"]
+    table, n_traj, n_steps = sweep_table(wl["n_sets"], seed=wl["seed"])
+    work = float((n_traj.astype(np.int64) * n_steps).sum())
+    ws = api.batched_workspace(n_traj, wl["bins"])
+    api.sweep(table, n_traj, n_steps, scheme=wl["scheme"], seed=wl["seed"], bins=wl["bins"], ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = api.sweep(table, n_traj, n_steps, scheme=wl["scheme"], seed=wl["seed"],
+                      bins=wl["bins"], ws=ws)
+    torch.cuda.synchronize()
+    t_sweep = (time.perf_counter() - t0) / reps
+
+    n, S = 1 << 20, 20_000
+    state, snap = api.State.empty(n), api.State.empty(n)
+    rws = api.reduce_workspace(n, wl["bins"])
+
+    def single():
+        api.reset_state(state, wl["seed"])
+        api.integrate(state, S, BASE_PARAMS, wl["dt"], wl["scheme"], wl["seed"], 0, 0, S // 2, snap,
+                      rws, wl["bins"])
+        api.reduce(rws, n, wl["bins"], S // 2 * wl["dt"])
+    single()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        single()
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / reps
+    v_sweep, v_single = work / t_sweep, n * S / t_single
+    return {"workload": "sweep-4096", "value": v_sweep, "unit": "particle-steps/s",
+            "ms": t_sweep * 1e3, "particle_steps": work, "scheme": wl["scheme"],
+            "single_set_value": v_single, "single_set_config": f"{n} particles x {S} steps",
+            "ratio_to_single_set": v_sweep / v_single,
+            "finite_sets": int(np.isfinite(r.mean_v).sum())}
+
+
+def adjoint_bench(reps: int = 3) -> dict:
+    """Cost of the checkpointed adjoint (forward with checkpoints + backward) relative to the
+    plain forward of the same ensemble: 65536 particles, 1e4 EM steps, W = 2000, K = 100."""
+    import torch
+
+    from paper_1104_2499_amd import adjoint, api
+    from paper_1104_2499_amd.workloads import BASE_PARAMS, WORKLOADS
+
+    wl = WORKLOADS["adjoint-64k"]
+    n, S, W, K = wl["n"], wl["steps"], wl["window"], wl["ckpt"]
+    stream = torch.cuda.current_stream()
+    cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=K, seed=wl["seed"])
+    theta = torch.tensor([[BASE_PARAMS[k] for k in adjoint.GRAD_KEYS]], dtype=torch.float64)
+    rows = adjoint.param_rows(theta, cfg)
+    ws = adjoint.workspace(1, cfg)
+    gloss = torch.ones(1, dtype=torch.float64, device="cuda")
+    state, snap = api.State.empty(n), api.State.empty(n)
+    rws = api.reduce_workspace(n, 0)
+
+    def plain():
+        api.reset_state(state, wl["seed"])
+        api.integrate(state, S, BASE_PARAMS, wl["dt"], "em", wl["seed"], 0, 0, S - W, snap, rws, 0)
+        return api.reduce(rws, n, 0, W * wl["dt"])[0]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_plain = timed(plain)
+    t_fwd = timed(lambda: adjoint.forward(rows, cfg, ws))
+    t_bwd = timed(lambda: adjoint.backward(rows, cfg, ws, gloss))
+    loss = float(adjoint.forward(rows, cfg, ws)[0].cpu())
+    mean_v = float(plain()[0].cpu())
+    return {"workload": "adjoint-64k", "plain_forward_ms": t_plain, "adjoint_forward_ms": t_fwd,
+            "adjoint_backward_ms": t_bwd, "cost_ratio": (t_fwd + t_bwd) / t_plain,
+            "loss_equals_forward_mean": loss == mean_v,
+            "particle_steps": n * S}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,8 +208,25 @@ def main() -> int:
     ap.add_argument("--sim-steps", type=int, default=None,
                     help="override the SDE step count (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 4096-set sweep line item")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 512 MiB device copy (reference for HBM counters)")
     ap.add_argument("--tune", default=None, help="block,ppl,unroll (default: library default)")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        # a plain device-to-device copy of known size: the reference that scales the HBM
+        # counters (FETCH_SIZE, WRITE_SIZE) of the integrator's profile
+        import torch
+
+        nbytes = 1 << 29
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "launches": 3}), flush=True)
+        return 0
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
@@ -183,14 +282,14 @@ def main() -> int:
     kern_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
     ps = n * S
     value = ps * args.steps / wall
-    rates = load_rates()
-    isa = ISA_HEUN if wl["scheme"] == "heun" else ISA_EM
-    slots = issue_cost(isa, rates)
-    kern_rate = ps / (kern_ms * 1e-3)
-    achieved = slots * kern_rate / 1e12
-    peak = VALU_LANE_SLOTS_PER_S / 1e12
-    kernel = "k_integrate_" + wl["scheme"]
+    scheme = wl["scheme"]
+    kern_rate = ps / (kern_ms * 1e-3)          # particle-steps/s of the integrator kernel
+    achieved = FLOP_PER_STEP[scheme] * kern_rate / 1e12
+    kernel = "k_integrate_" + scheme
     traffic = load_traffic(kernel, args.workload)
+    lane_instr = VALU_INSTR_PER_STEP[scheme] * kern_rate
+    trans_rate = TRANS_PER_STEP[scheme] * kern_rate
+    trans_peak = N_SIMD * 64 / (TRANS_NS_PER_WAVE_INSTR * 1e-9)
     o = out.cpu()
     line = {
         "metric": "particle-steps/s (FP32) and % VALU peak",
@@ -208,16 +307,23 @@ def main() -> int:
         "config": {"workload": args.workload, "particles": n, "sde_steps": S, "scheme": wl["scheme"],
                    "dt": dt, "window": W, "bins": bins, "seed": seed, "params": BASE_PARAMS,
                    "tuning": tune or "default"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
-                     "frac": achieved / peak, "traffic": traffic,
-                     "kernel": kernel, "kernel_ms": kern_ms,
-                     "slots_per_particle_step": slots, "issue_rates": rates,
-                     "fp32_tflops": FLOP_PER_STEP[wl["scheme"]] * kern_rate / 1e12,
-                     "fp32_flop_frac": FLOP_PER_STEP[wl["scheme"]] * kern_rate / 1e12
-                     / FP32_VECTOR_PEAK_TFLOPS},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic, "kernel": kernel, "kernel_ms": kern_ms,
+                     "flop_per_particle_step": FLOP_PER_STEP[scheme],
+                     "valu_issue": {"instr_per_particle_step": VALU_INSTR_PER_STEP[scheme],
+                                    "lane_instr_per_s": lane_instr,
+                                    "frac_of_one_wave_instr_per_4_cycles":
+                                        lane_instr / VALU_LANE_INSTR_PER_S},
+                     "transcendental": {"per_particle_step": TRANS_PER_STEP[scheme],
+                                        "per_s": trans_rate, "peak_per_s": trans_peak,
+                                        "frac": trans_rate / trans_peak}},
         "result": {"mean_v": float(o[0]), "stderr": float(o[1]),
                    "hist_total": int(hist.sum().item())},
     }
+    if not args.no_sweep:
+        line["sweep"] = sweep_bench()
+        line["adjoint"] = adjoint_bench()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, BASE_PARAMS)
     print(json.dumps(line), flush=True)

@@ -291,11 +291,13 @@ void orc_rk4(const orc_params *p, double dt, int64_t n_steps, int64_t n, double 
  * The whole trajectory of a particle is stored (no checkpoints); lambda_n = dJ/dy_n is carried
  * from n = S down to 0 through the transposed Jacobian of the step, and the explicit parameter
  * derivatives of each step are accumulated. Gradient order: (U0, a, D, d2, q, c).
+ * eps != 0 records the forward path under the rounding-sensitivity model (see perturb) and
+ * linearises around that path, which measures how well-conditioned each particle's gradient is.
  * Returns -1 on bad input (D must be > 0 since dsigma/dD is singular at D = 0).
  * ------------------------------------------------------------------------------------------- */
 int orc_adjoint(const orc_params *p, double dt, int64_t n_steps, int64_t window, uint64_t seed,
                 uint32_t set, int64_t n, const uint32_t *ids, const double *x0, const double *v0,
-                const double *e0, double *J, double *grad)
+                const double *e0, double *J, double *grad, double eps)
 {
     if (!(dt > 0.0) || n_steps < 1 || window < 1 || window > n_steps || !(p->D > 0.0))
         return -1;
@@ -322,6 +324,8 @@ int orc_adjoint(const orc_params *p, double dt, int64_t n_steps, int64_t window,
         for (int64_t k = 0; k < n_steps; ++k) {
             tx[k] = y[0]; tv[k] = y[1]; te[k] = y[2];
             one_step(p, ORC_EM, dt, sig, tz[k], y);
+            if (eps != 0.0)
+                perturb(seed, pid, set, k, eps, y);
         }
         tx[n_steps] = y[0]; tv[n_steps] = y[1]; te[n_steps] = y[2];
         J[i] = (tx[n_steps] - tx[wb]) * jscale;

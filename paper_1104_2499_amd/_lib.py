@@ -44,6 +44,11 @@ class AbpBatch(ctypes.Structure):
                 ("n_bins", ctypes.c_int32)]
 
 
+class AbpAdjointCfg(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("n_steps", ctypes.c_int64), ("window", ctypes.c_int64),
+                ("ckpt_every", ctypes.c_int64), ("seed", ctypes.c_uint64)]
+
+
 _P = ctypes.POINTER
 _vp, _i32, _i64, _u32, _u64, _f64, _sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                           ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
@@ -63,6 +68,9 @@ SIGNATURES = {
     "abp_batched_workspace_bytes": (_sz, [_i32, _vp, _i32]),
     "abp_integrate_batched": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _P(AbpBatch),
                                              _P(AbpTuning), _vp, _sz, _vp, _vp, _vp]),
+    "abp_adjoint_workspace_bytes": (_sz, [_i32, _i64, _i64, _i64]),
+    "abp_adjoint": (ctypes.c_int, [_i32, _i32, _vp, _i64, _P(AbpAdjointCfg), _vp, _sz, _vp, _vp,
+                                   _vp, _vp, _vp]),
 }
 
 

@@ -1,0 +1,415 @@
+// adjoint.hip -- pathwise gradients of the window mean velocity through the Euler-Maruyama map
+// (Eqs. (1)-(3)), by a discrete adjoint with checkpointing and noise regeneration.
+//
+// Loss of set k: L_k = (1/N) sum_i J_i, J_i = (x_S - x_{S-W}) / (W dt), i.e. the mean drift
+// velocity that abp_integrate reports for the same set (bit for bit). Gradient order:
+// (U0, a, D, d2, q, c).
+//
+// Forward phase: each lane integrates its particle from the workload initial condition and stores
+// its whole state (28 bytes) every K steps. Backward phase: for each segment [jK, (j+1)K) in
+// reverse, the lane restores the checkpoint and recomputes the segment with regenerated Philox
+// noise, leaving sub-checkpoints at absolute multiples of B steps in workspace memory; then, for
+// each sub-window in reverse, it restores the sub-checkpoint, recomputes the sub-window while
+// staging the values the reverse step needs (cos and sin of the phase, v, e, sigma*xi) in
+// registers, and runs the adjoint recursion backwards over it. The recomputation reproduces the
+// forward bits exactly (the integrator's state is resumable mid-block), so the result does not
+// depend on K. Per-step gradient terms are summed in FP32 within each absolute B-step window and
+// in FP64 across windows (that grouping does not depend on K either); tiles of 64 particles and
+// sets are then reduced in a fixed order.
+//
+// Workspace layout (abp_adjoint_workspace_bytes):
+//   AdjRow rows[n_sets] | float ckpt[n_seg][7][N] | float sub[n_sub][7][N] |
+//   double loss_part[n_sets][tiles][2] | double grad_part[n_sets][tiles][6]
+// (N = n_sets * tiles * 64 checkpoint slots: one per lane, also past a set's last particle)
+#include <vector>
+
+#include "reduce.hpp"
+
+namespace abp {
+
+// Per-set constants of the reverse step (derivatives of the drift), FP32.
+struct RevCoef {
+    float two_pi;      // 2 pi                (dU'/dU0 = 2 pi (c + 2a cos 2th))
+    float four_pi_U0;  // 4 pi U0             (dU'/da  = 4 pi U0 cos 2th)
+    float a2;          // 2a
+    float eight_a;     // 8a                  (U'' = -4 pi^2 U0 sin th (1 + 8a cos th))
+    float m4pi2U0;     // -4 pi^2 U0
+    float inv2D;       // 1 / (2D)            (d(sigma xi)/dD = sigma xi / (2D))
+};
+
+struct AdjRow {
+    Coef k;
+    RevCoef r;
+    uint32_t pad[3];
+};
+
+struct AdjArgs {
+    const AdjRow *rows;
+    float *ckpt;        // [n_seg][7][N]
+    float *sub;         // [n_sub][7][N]
+    double *loss_part;  // [n_sets][tiles][2]
+    double *grad_part;  // [n_sets][tiles][6]
+    const double *gloss;
+    double *loss;
+    double *grad;
+    double *grad_particles;  // optional [n_sets][n][6]: dJ_i/dtheta per particle
+    int64_t n;          // particles per set
+    int64_t N;          // checkpoint slots (64 per tile)
+    int64_t tiles;      // tiles per set
+    int64_t S, W, K;    // steps, window, checkpoint interval
+    int64_t n_sub;      // sub-checkpoint slots per segment
+    double dt;
+    uint32_t k0, k1;
+    int32_t n_sets;
+};
+
+constexpr int kStage = 8;  // B: steps staged in registers per sub-window (multiple of 4)
+
+struct AdjLayout {
+    size_t rows, ckpt, sub, loss, grad, total;
+    int64_t n_seg, n_sub, tiles;
+};
+
+// Every lane of every wave (also lanes past a set's last particle) owns one slot in the
+// checkpoint planes: N = n_sets * tiles * 64.
+inline AdjLayout adj_layout(int32_t n_sets, int64_t n, int64_t S, int64_t K)
+{
+    AdjLayout L;
+    L.n_seg = (S + K - 1) / K;
+    L.n_sub = (K + kStage - 1) / kStage + 1;
+    L.tiles = (n + 63) / 64;
+    const size_t N = (size_t)n_sets * (size_t)L.tiles * 64;
+    L.rows = 0;
+    L.ckpt = align_up(sizeof(AdjRow) * (size_t)n_sets, 256);
+    L.sub = align_up(L.ckpt + sizeof(float) * 7 * N * (size_t)L.n_seg, 256);
+    L.loss = align_up(L.sub + sizeof(float) * 7 * N * (size_t)L.n_sub, 256);
+    L.grad = align_up(L.loss + sizeof(double) * 2 * (size_t)n_sets * (size_t)L.tiles, 256);
+    L.total = align_up(L.grad + sizeof(double) * 6 * (size_t)n_sets * (size_t)L.tiles, 256);
+    return L;
+}
+
+// Whole particle state in 7 planes of N floats (cell stored as its bit pattern).
+__device__ __forceinline__ void put_state(float *base, int64_t N, int64_t g, const Particle &p)
+{
+    base[g] = __int_as_float(p.cell);
+    base[N + g] = p.xf;
+    base[2 * N + g] = p.v;
+    base[3 * N + g] = p.e;
+    base[4 * N + g] = p.lx;
+    base[5 * N + g] = p.lv;
+    base[6 * N + g] = p.le;
+}
+
+__device__ __forceinline__ Particle get_state(const float *base, int64_t N, int64_t g)
+{
+    Particle p;
+    p.cell = __float_as_int(base[g]);
+    p.xf = base[N + g];
+    p.v = base[2 * N + g];
+    p.e = base[3 * N + g];
+    p.lx = base[4 * N + g];
+    p.lv = base[5 * N + g];
+    p.le = base[6 * N + g];
+    return p;
+}
+
+// The lane's place: wave w of the grid covers tile (w mod tiles) of set (w / tiles).
+struct Lane {
+    int lane;
+    int32_t set;
+    int64_t tile, i, g;
+    bool live;
+};
+
+__device__ __forceinline__ bool locate(const AdjArgs &a, Lane &L)
+{
+    L.lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (wave >= (int64_t)a.n_sets * a.tiles)
+        return false;  // wavefront-uniform
+    L.set = (int32_t)(wave / a.tiles);
+    L.tile = wave - (int64_t)L.set * a.tiles;
+    L.i = L.tile * 64 + L.lane;
+    L.live = L.i < a.n;
+    L.g = wave * 64 + L.lane;
+    return true;
+}
+
+__device__ __forceinline__ Particle initial_particle(uint32_t pid, uint32_t set, uint32_t k0,
+                                                     uint32_t k1)
+{
+    const Philox4 r = philox4x32_10(0u, pid, set, kDomainInit, k0, k1);
+    Particle p;
+    p.cell = 0;
+    p.xf = (float)(r.w[0] >> 8) * 0x1p-24f;
+    p.v = p.e = 0.0f;
+    p.lx = p.lv = p.le = 0.0f;
+    return p;
+}
+
+// Forward phase: integrate, store a checkpoint at every multiple of K, reduce the loss.
+__global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
+{
+    Lane L;
+    if (!locate(a, L))
+        return;
+    const AdjRow &row = a.rows[L.set];
+    const Stream s{a.k0, a.k1, (uint32_t)L.set};
+    const uint32_t pid[1] = {(uint32_t)L.i};
+    Particle p[1] = {initial_particle(pid[0], (uint32_t)L.set, a.k0, a.k1)};
+    const int64_t wb = a.S - a.W;
+    double xs[1] = {0.0}, xe[1];
+    int64_t step = 0;
+    for (int64_t j = 0; j * a.K < a.S; ++j) {
+        put_state(a.ckpt + (size_t)j * 7 * a.N, a.N, L.g, p[0]);
+        const int64_t end = (j + 1) * a.K < a.S ? (j + 1) * a.K : a.S;
+        if (wb >= step && wb < end) {
+            advance<0, 1, 1>(row.k, s, pid, p, step, wb);
+            xs[0] = position64(p[0].cell, p[0].xf, p[0].lx);
+        }
+        advance<0, 1, 1>(row.k, s, pid, p, step, end);
+    }
+    if (wb == a.S)
+        xs[0] = position64(p[0].cell, p[0].xf, p[0].lx);
+    xe[0] = position64(p[0].cell, p[0].xf, p[0].lx);
+    const bool live[1] = {L.live};
+    reduce_tiles<1>(xe, xs, live, L.tile, a.n, L.lane, 0, a.loss_part + 2 * L.set * a.tiles,
+                    nullptr);
+}
+
+// Staged values of one step for the reverse sweep.
+struct Stage {
+    float c, s, v, e, z;
+};
+
+// Backward phase. lam = dJ_i/dy_{n+1} while step n is reversed.
+__global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
+{
+    Lane L;
+    if (!locate(a, L))
+        return;
+    const AdjRow &row = a.rows[L.set];
+    const Coef &k = row.k;
+    const RevCoef &rc = row.r;
+    const Stream s{a.k0, a.k1, (uint32_t)L.set};
+    const uint32_t pid[1] = {(uint32_t)L.i};
+    const int64_t wb = a.S - a.W;
+    const float jscale = (float)(1.0 / ((double)a.W * a.dt));
+    float lx = jscale, lv = 0.0f, le = 0.0f;
+    float g32[6] = {0, 0, 0, 0, 0, 0};
+    double g64[6] = {0, 0, 0, 0, 0, 0};
+    float *sub = a.sub;
+
+    const int64_t n_seg = (a.S + a.K - 1) / a.K;
+    for (int64_t j = n_seg - 1; j >= 0; --j) {
+        const int64_t s0 = j * a.K;
+        const int64_t s1 = s0 + a.K < a.S ? s0 + a.K : a.S;
+        const int64_t m0 = s0 / kStage, m1 = (s1 - 1) / kStage;
+        // level 1: recompute the segment, leaving a sub-checkpoint at each sub-window start
+        Particle p[1] = {get_state(a.ckpt + (size_t)j * 7 * a.N, a.N, L.g)};
+        int64_t step = s0;
+        for (int64_t m = m0; m <= m1; ++m) {
+            put_state(sub + (size_t)(m - m0) * 7 * a.N, a.N, L.g, p[0]);
+            const int64_t e = (m + 1) * kStage < s1 ? (m + 1) * kStage : s1;
+            advance<0, 1, 1>(k, s, pid, p, step, e);
+        }
+        // level 2: sub-windows in reverse
+        for (int64_t m = m1; m >= m0; --m) {
+            const int64_t base = m * kStage;
+            const int lo = (int)((s0 > base ? s0 : base) - base);
+            const int hi = (int)(((m + 1) * kStage < s1 ? (m + 1) * kStage : s1) - base);
+            Particle q = get_state(sub + (size_t)(m - m0) * 7 * a.N, a.N, L.g);
+            Stage st[kStage];
+            Noise4 z;
+            float xb = q.xf + k.phi;
+#pragma unroll
+            for (int t = 0; t < kStage; ++t) {
+                if (t >= lo && t < hi) {
+                    if ((t & 3) == 0 || t == lo)
+                        z = noise_block((uint32_t)((base + t) >> 2), pid[0], s.set, s.k0, s.k1,
+                                        k.sigma);
+                    const float xc = xb + q.lx, vc = q.v + q.lv, ec = q.e + q.le;
+                    st[t].c = __builtin_amdgcn_cosf(xc);
+                    st[t].s = __builtin_amdgcn_sinf(xc);
+                    st[t].v = vc;
+                    st[t].e = ec;
+                    st[t].z = z.z[t & 3];
+                    step_em(k, q, xb, z.z[t & 3]);
+                    if ((t & 3) == 3) {
+                        end_block(q);
+                        xb = q.xf + k.phi;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = kStage - 1; t >= 0; --t) {
+                if (t >= lo && t < hi) {
+                    const int64_t n = base + t;
+                    if (n + 1 == wb)
+                        lx -= jscale;  // the window-start position enters J with weight -1/(W dt)
+                    const float c = st[t].c, sn = st[t].s, v = st[t].v, e = st[t].e;
+                    const float c2 = fmaf(2.0f * c, c, -1.0f);  // cos 2th
+                    const float upp = rc.m4pi2U0 * sn * fmaf(rc.eight_a, c, 1.0f);
+                    const float lvdt = lv * k.dt, ledt = le * k.dt;
+                    const float ev = e * v;
+                    g32[0] = fmaf(-lvdt * rc.two_pi, fmaf(rc.a2, c2, c), g32[0]);
+                    g32[1] = fmaf(-lvdt * rc.four_pi_U0, c2, g32[1]);
+                    g32[2] = fmaf(lv * st[t].z, rc.inv2D, g32[2]);
+                    g32[3] = fmaf(lvdt, ev, fmaf(-ledt * ev, v, g32[3]));
+                    g32[4] += ledt;
+                    g32[5] = fmaf(-ledt, e, g32[5]);
+                    const float nlx = fmaf(-lvdt, upp, lx);
+                    const float nlv = fmaf(lx, k.dt, fmaf(lvdt, fmaf(k.d2, e, -k.g0), lv)) -
+                                      2.0f * k.d2 * ledt * ev;
+                    const float nle = fmaf(lvdt * k.d2, v, fmaf(-ledt, fmaf(k.d2 * v, v, k.c), le));
+                    lx = nlx;
+                    lv = nlv;
+                    le = nle;
+                    if (t == 0) {
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) {
+                            g64[r] += (double)g32[r];
+                            g32[r] = 0.0f;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (a.grad_particles && L.live) {
+        double *gp = a.grad_particles + 6 * ((int64_t)L.set * a.n + L.i);
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+            gp[r] = g64[r];
+    }
+    // tile partials of the six gradient components (lanes past the end hold zeros)
+    if (L.tile * 64 < a.n) {
+        double *gp = a.grad_part + 6 * ((int64_t)L.set * a.tiles + L.tile);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            const double t = wave_sum(L.live ? g64[r] : 0.0);
+            if (L.lane == 0)
+                gp[r] = t;
+        }
+    }
+}
+
+// One wavefront per set: loss = mean over particles of J_i; grad = gloss / N * sum of tiles.
+__global__ __launch_bounds__(64) void k_adj_finalize(AdjArgs a, int32_t phase)
+{
+    const int32_t k = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    if (phase == 0) {
+        double o[2];
+        finalize_set(a.loss_part + 2 * (int64_t)k * a.tiles, a.tiles, a.n, (double)a.W * a.dt, o);
+        if (lane == 0)
+            a.loss[k] = o[0];
+        return;
+    }
+    const double *gp = a.grad_part + 6 * (int64_t)k * a.tiles;
+    const double scale = a.gloss[k] / (double)a.n;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        double acc = 0.0;
+        for (int64_t t = lane; t < a.tiles; t += 64)
+            acc += gp[6 * t + r];
+        acc = wave_sum(acc);
+        if (lane == 0)
+            a.grad[6 * (int64_t)k + r] = acc * scale;
+    }
+}
+
+}  // namespace abp
+
+using namespace abp;
+
+extern "C" size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set, int64_t n_steps,
+                                              int64_t ckpt_every)
+{
+    if (n_sets < 1 || n_per_set < 1 || n_steps < 1 || ckpt_every < 1 ||
+        (int64_t)n_sets * n_per_set > kMaxParticles || n_steps > kMaxStepIndex)
+        return 0;
+    return adj_layout(n_sets, n_per_set, n_steps, ckpt_every).total;
+}
+
+extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_params *h_params,
+                                  int64_t n_per_set, const abp_adjoint_cfg *cfg, void *d_ws,
+                                  size_t ws_bytes, double *d_loss, const double *d_gloss,
+                                  double *d_grad, double *d_grad_particles, void *stream)
+{
+    if ((phase != 0 && phase != 1) || !h_params || !cfg || n_sets < 1 || n_per_set < 1 ||
+        (int64_t)n_sets * n_per_set > kMaxParticles || n_per_set > 0xFFFFFFFFll)
+        return ABP_E_ARG;
+    if (!(cfg->dt > 0.0) || !is_finite(cfg->dt) || cfg->n_steps < 1 ||
+        cfg->n_steps > kMaxStepIndex || cfg->window < 1 || cfg->window > cfg->n_steps ||
+        cfg->ckpt_every < 1)
+        return ABP_E_ARG;
+    for (int32_t k = 0; k < n_sets; ++k)
+        if (!params_ok(h_params[k]) || !(h_params[k].D > 0.0))
+            return ABP_E_ARG;
+    if (!d_ws || !aligned(d_ws, 256))
+        return ABP_E_ARG;
+    if (phase == 0 && (!d_loss || !aligned(d_loss, 8)))
+        return ABP_E_ARG;
+    if (phase == 1 && (!d_gloss || !d_grad || !aligned(d_gloss, 8) || !aligned(d_grad, 8) ||
+                       !aligned(d_grad_particles, 8)))
+        return ABP_E_ARG;
+    const AdjLayout L = adj_layout(n_sets, n_per_set, cfg->n_steps, cfg->ckpt_every);
+    if (ws_bytes < L.total)
+        return ABP_E_WORKSPACE;
+    if (abp_status st = check_device())
+        return st;
+
+    std::vector<AdjRow> rows((size_t)n_sets);
+    for (int32_t k = 0; k < n_sets; ++k) {
+        const abp_params &p = h_params[k];
+        AdjRow &r = rows[(size_t)k];
+        std::memset(&r, 0, sizeof r);
+        r.k = make_coef(p, cfg->dt);
+        r.r.two_pi = (float)(2.0 * kPi);
+        r.r.four_pi_U0 = (float)(4.0 * kPi * p.U0);
+        r.r.a2 = (float)(2.0 * p.a);
+        r.r.eight_a = (float)(8.0 * p.a);
+        r.r.m4pi2U0 = (float)(-4.0 * kPi * kPi * p.U0);
+        r.r.inv2D = (float)(1.0 / (2.0 * p.D));
+    }
+    hipStream_t st = as_stream(stream);
+    char *ws = reinterpret_cast<char *>(d_ws);
+    if (hipMemcpyAsync(ws + L.rows, rows.data(), sizeof(AdjRow) * rows.size(),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return ABP_E_HIP;  // the staged rows live in this call's host memory
+
+    AdjArgs a{};
+    a.rows = reinterpret_cast<const AdjRow *>(ws + L.rows);
+    a.ckpt = reinterpret_cast<float *>(ws + L.ckpt);
+    a.sub = reinterpret_cast<float *>(ws + L.sub);
+    a.loss_part = reinterpret_cast<double *>(ws + L.loss);
+    a.grad_part = reinterpret_cast<double *>(ws + L.grad);
+    a.gloss = d_gloss;
+    a.loss = d_loss;
+    a.grad = d_grad;
+    a.grad_particles = phase == 1 ? d_grad_particles : nullptr;
+    a.n = n_per_set;
+    a.N = (int64_t)n_sets * L.tiles * 64;
+    a.dt = cfg->dt;
+    a.tiles = L.tiles;
+    a.S = cfg->n_steps;
+    a.W = cfg->window;
+    a.K = cfg->ckpt_every;
+    a.n_sub = L.n_sub;
+    const Stream ks = make_stream(cfg->seed, 0);
+    a.k0 = ks.k0;
+    a.k1 = ks.k1;
+    a.n_sets = n_sets;
+    const int64_t waves = (int64_t)n_sets * L.tiles;
+    const unsigned grid = (unsigned)((waves * 64 + 255) / 256);
+    if (phase == 0)
+        hipLaunchKernelGGL(k_adj_forward, dim3(grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_adj_backward, dim3(grid), dim3(256), 0, st, a);
+    if (hipGetLastError() != hipSuccess)
+        return ABP_E_HIP;
+    hipLaunchKernelGGL(k_adj_finalize, dim3((unsigned)n_sets), dim3(64), 0, st, a, phase);
+    return launch_status();
+}

@@ -25,14 +25,14 @@
 
 enum Op {
     FMA, ADD, MUL, COS, LOG, SQRT, MAD64, MULHI, MULLO, BITOP3, ADDU, CVT, FMA64,
-    MIX_FMA_COS, MIX_FMA_MAD64, MIX_FMA_BITOP3, MIX_COS_MAD64, N_OPS
+    MIX_FMA_COS, MIX_FMA_MAD64, MIX_FMA_BITOP3, MIX_COS_MAD64, FMAMK, N_OPS
 };
 static const char *kNames[N_OPS] = {
-    "v_fma_f32", "v_add_f32", "v_mul_f32", "v_cos_f32", "v_log_f32", "v_sqrt_f32",
+    "v_fma_f32(3v)", "v_add_f32", "v_mul_f32", "v_cos_f32", "v_log_f32", "v_sqrt_f32",
     "mad_u64+mov", "v_mul_hi_u32", "v_mul_lo_u32", "v_bitop3_b32", "v_add_u32",
-    "v_cvt_f32_u32", "v_fma_f64", "fma+cos", "fma+mad64+mov", "fma+bitop3", "cos+mad64+mov"};
+    "v_cvt_f32_u32", "v_fma_f64", "fma+cos", "fma+mad64+mov", "fma+bitop3", "cos+mad64+mov", "v_fmamk_f32"};
 // v_mad_u64_u32 chains carry one v_mov_b32 each (the zero high word of the addend)
-static const int kInstr[N_OPS] = {1, 1, 1, 1, 1, 1, 2, 1, 1, 1, 1, 1, 1, 2, 3, 2, 3};
+static const int kInstr[N_OPS] = {1, 1, 1, 1, 1, 1, 2, 1, 1, 1, 1, 1, 1, 2, 3, 2, 3, 1};
 
 __device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c)
 {
@@ -65,11 +65,15 @@ __global__ __launch_bounds__(256) void k_rate(float *out, float seedf, uint32_t 
             else if constexpr (OP == SQRT) f[c] = __builtin_amdgcn_sqrtf(f[c]);
             else if constexpr (OP == MAD64) w[c] = mad64((uint32_t)w[c], m, w[c] >> 32);
             else if constexpr (OP == MULHI) u[c] = __umulhi(u[c], m);
-            else if constexpr (OP == MULLO) u[c] = u[c] * m;
+            else if constexpr (OP == MULLO)  // asm: keeps the chain from being folded
+                asm volatile("v_mul_lo_u32 %0, %1, %2" : "=v"(u[c]) : "v"(u[c]), "v"(m));
             else if constexpr (OP == BITOP3)
                 u[c] = __builtin_amdgcn_bitop3_b32(u[c], m, (uint32_t)c, 0x96);
-            else if constexpr (OP == ADDU) u[c] = u[c] + m;
-            else if constexpr (OP == CVT) f[c] = (float)__float_as_uint(f[c]);
+            else if constexpr (OP == ADDU)
+                asm volatile("v_add_u32 %0, %1, %2" : "=v"(u[c]) : "v"(u[c]), "v"(m));
+            else if constexpr (OP == CVT)
+                asm volatile("v_cvt_f32_u32 %0, %1" : "=v"(f[c]) : "v"(f[c]));
+            else if constexpr (OP == FMAMK) f[c] = fmaf(f[c], 0.999f, h);
             else if constexpr (OP == FMA64) d[c] = fma(d[c], (double)g, (double)h);
             if constexpr (OP == MIX_FMA_COS) {
                 // independent FMA and cos chains, interleaved
@@ -128,7 +132,7 @@ int main()
     float *d_out = nullptr;
     CHECK(hipMalloc(&d_out, sizeof(float) * (size_t)cus * 8 * 256));
     using T = Table<FMA, ADD, MUL, COS, LOG, SQRT, MAD64, MULHI, MULLO, BITOP3, ADDU, CVT, FMA64,
-                    MIX_FMA_COS, MIX_FMA_MAD64, MIX_FMA_BITOP3, MIX_COS_MAD64>;
+                    MIX_FMA_COS, MIX_FMA_MAD64, MIX_FMA_BITOP3, MIX_COS_MAD64, FMAMK>;
     std::printf("# device: %s, %d CUs, max clock %d kHz; %d chains x %d iterations per lane\n",
                 prop.gcnArchName, cus, prop.clockRate, CHAINS, ITERS);
     const double instr_per_wave = (double)ITERS * CHAINS;
@@ -136,7 +140,7 @@ int main()
     for (int wps : {1, 2, 4, 8}) {
         const int grid = cus * wps;  // 4 waves per block: wps waves per SIMD
         for (int op = 0; op < N_OPS; ++op) {
-            if (wps != 8 && op != FMA && op != COS && op != MAD64)
+            if (wps != 8 && op != FMA && op != COS && op != MAD64 && op != FMAMK)
                 continue;
             const double ms = time_kernel(T::k[op], d_out, grid);
             const double ns = ms * 1e6 / (wps * instr_per_wave * kInstr[op]);
@@ -146,7 +150,10 @@ int main()
                         kNames[op], wps, ms, ns);
         }
     }
-    const double fma = ns8[FMA];
+    // reference slot: the fastest plain FP32 op (register-operand FMA is limited by VGPR reads)
+    double fma = ns8[FMAMK];
+    if (ns8[ADD] < fma) fma = ns8[ADD];
+    if (ns8[MUL] < fma) fma = ns8[MUL];
     std::printf("fma_ns: %.4f\n", fma);
     std::printf("fma_cycles_at_max_clock: %.3f\n", fma * prop.clockRate * 1e-6);
     std::printf("trans_slots: %.3f\n", (ns8[COS] + ns8[LOG] + ns8[SQRT]) / 3.0 / fma);
