@@ -176,8 +176,13 @@ typedef struct abp_adjoint_cfg {
     double dt;           /* > 0 */
     int64_t n_steps;     /* S >= 1 */
     int64_t window;      /* W, 1 <= W <= S: the loss averages over the last W steps */
-    int64_t ckpt_every;  /* K >= 1: forward checkpoint interval (e.g. about sqrt(S)) */
+    int64_t ckpt_every;  /* K >= 1: forward checkpoint interval (e.g. about sqrt(S)); rounded up
+                            to a multiple of 16, the backward pass's register-staging window. The
+                            gradient does not depend on K (bit for bit) */
     uint64_t seed;       /* Philox key; set k uses counter word 2 = k */
+    int64_t lookback;    /* 0: exact pathwise gradient. T > 0: each window velocity's sensitivity
+                            is damped by (1 - 1/T) per step of look-back (a biased, bounded-variance
+                            estimator for long chaotic horizons) */
 } abp_adjoint_cfg;
 
 /* Bytes of workspace: checkpoints (28 bytes per particle per segment), sub-checkpoints, and the

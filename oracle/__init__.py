@@ -68,7 +68,7 @@ def _load():
     lib.orc_reduce.argtypes = [i64, vp, vp, f64, i32, vp, vp]
     lib.orc_rk4.argtypes = [P(_Params), f64, i64, i64, vp, vp, vp]
     lib.orc_adjoint.argtypes = [P(_Params), f64, i64, i64, u64, u32, i64, vp, vp, vp, vp, vp, vp,
-                                f64]
+                                f64, i64]
     lib.orc_adjoint.restype = ctypes.c_int
     lib.orc_complex_step.argtypes = [P(_Params), ctypes.c_int, f64, f64, i64, i64, u64, u32, i64,
                                      vp, vp, vp, vp, vp, vp]
@@ -182,10 +182,11 @@ def rk4(params: dict | None, x, v, e, n_steps: int, dt: float):
 
 
 def adjoint(params: dict | None, x0, v0, e0, n_steps: int, window: int, dt: float = 1e-3,
-            seed: int = 42, set_id: int = 0, ids=None, eps: float = 0.0):
+            seed: int = 42, set_id: int = 0, ids=None, eps: float = 0.0, lookback: int = 0):
     """Per-particle J_i = (x_S - x_{S-W})/(W dt) and dJ_i/d(U0, a, D, d2, q, c) [n, 6] by the
     discrete adjoint of Euler-Maruyama with the full trajectory stored. eps != 0 linearises around
-    the path perturbed by the rounding-sensitivity model (a conditioning probe)."""
+    the path perturbed by the rounding-sensitivity model (a conditioning probe). lookback = T > 0
+    gives the decayed estimator (each window velocity's sensitivity damped by 1 - 1/T per step)."""
     x0 = np.ascontiguousarray(x0, dtype=np.float64)
     v0 = np.ascontiguousarray(v0, dtype=np.float64)
     e0 = np.ascontiguousarray(e0, dtype=np.float64)
@@ -194,7 +195,8 @@ def adjoint(params: dict | None, x0, v0, e0, n_steps: int, window: int, dt: floa
     ids = _ids(ids, n)
     p = _params(params)
     rc = _load().orc_adjoint(ctypes.byref(p), dt, n_steps, window, seed, set_id, n, _ptr(ids),
-                             _ptr(x0), _ptr(v0), _ptr(e0), _ptr(J), _ptr(g), float(eps))
+                             _ptr(x0), _ptr(v0), _ptr(e0), _ptr(J), _ptr(g), float(eps),
+                             int(lookback))
     if rc != 0:
         raise ValueError(f"oracle adjoint failed (rc={rc})")
     return J, g

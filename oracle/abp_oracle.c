@@ -293,11 +293,12 @@ void orc_rk4(const orc_params *p, double dt, int64_t n_steps, int64_t n, double 
  * derivatives of each step are accumulated. Gradient order: (U0, a, D, d2, q, c).
  * eps != 0 records the forward path under the rounding-sensitivity model (see perturb) and
  * linearises around that path, which measures how well-conditioned each particle's gradient is.
+ * lookback = T > 0 computes the decayed estimator described at the recursion below.
  * Returns -1 on bad input (D must be > 0 since dsigma/dD is singular at D = 0).
  * ------------------------------------------------------------------------------------------- */
 int orc_adjoint(const orc_params *p, double dt, int64_t n_steps, int64_t window, uint64_t seed,
                 uint32_t set, int64_t n, const uint32_t *ids, const double *x0, const double *v0,
-                const double *e0, double *J, double *grad, double eps)
+                const double *e0, double *J, double *grad, double eps, int64_t lookback)
 {
     if (!(dt > 0.0) || n_steps < 1 || window < 1 || window > n_steps || !(p->D > 0.0))
         return -1;
@@ -330,11 +331,17 @@ int orc_adjoint(const orc_params *p, double dt, int64_t n_steps, int64_t window,
         tx[n_steps] = y[0]; tv[n_steps] = y[1]; te[n_steps] = y[2];
         J[i] = (tx[n_steps] - tx[wb]) * jscale;
 
-        double lx = jscale, lv = 0.0, le = 0.0;
+        /* Exact gradient (lookback = 0): J = (x_S - x_wb) s with s = 1/(W dt) enters lambda at
+         * x_S and x_wb. Decayed estimator (lookback = T > 0): J is written as (1/W) sum of v_k for
+         * k >= wb (the same function of the EM path), each v_k's sensitivity carried back with an
+         * extra factor rho = 1 - 1/T per step. */
+        const int vform = lookback > 0;
+        const double rho = vform ? 1.0 - 1.0 / (double)lookback : 1.0;
+        double lx = vform ? 0.0 : jscale, lv = 0.0, le = 0.0;
         double g[6] = {0, 0, 0, 0, 0, 0};
         for (int64_t k = n_steps - 1; k >= 0; --k) {
             /* lambda currently holds dJ/dy_{k+1}; the snapshot term enters at index wb. */
-            if (k + 1 == wb)
+            if (k + 1 == wb && !vform)
                 lx -= jscale;
             double xk = tx[k], vk = tv[k], ek = te[k];
             double th = 2.0 * ORC_PI * (xk + p->phi);
@@ -350,9 +357,15 @@ int orc_adjoint(const orc_params *p, double dt, int64_t n_steps, int64_t window,
             double nlv = lx * dt + lv * (1.0 + (p->d2 * ek - p->gamma0) * dt) +
                          le * (-2.0 * p->d2 * ek * vk * dt);
             double nle = lv * (p->d2 * vk * dt) + le * (1.0 - (p->c + p->d2 * vk * vk) * dt);
-            lx = nlx; lv = nlv; le = nle;
+            if (vform) {
+                lx = rho * nlx;
+                lv = rho * nlv + (k >= wb ? 1.0 / (double)window : 0.0);
+                le = rho * nle;
+            } else {
+                lx = nlx; lv = nlv; le = nle;
+            }
         }
-        if (wb == 0)
+        if (wb == 0 && !vform)
             lx -= jscale;
         (void)lx;
         for (int j = 0; j < 6; ++j)

@@ -46,7 +46,8 @@ class AbpBatch(ctypes.Structure):
 
 class AbpAdjointCfg(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("n_steps", ctypes.c_int64), ("window", ctypes.c_int64),
-                ("ckpt_every", ctypes.c_int64), ("seed", ctypes.c_uint64)]
+                ("ckpt_every", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("lookback", ctypes.c_int64)]
 
 
 _P = ctypes.POINTER
@@ -82,10 +83,15 @@ _lib = None
 
 
 def load(path: str = LIB_PATH):
-    """Load libabp.so once and attach the signatures."""
+    """Load libabp.so once and attach the signatures.
+
+    torch is imported first so that libabp.so binds to the HIP runtime torch has loaded (both
+    carry the soname libamdhip64.so.7): the library runs on torch's streams and memory, and one
+    process must not hold two HIP runtimes."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise LibraryMissing(
             f"{path} is not built; run `python -m paper_1104_2499_amd.build` (hipcc, gfx950)")

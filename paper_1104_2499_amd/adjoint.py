@@ -29,11 +29,13 @@ class AdjointConfig:
     ckpt: int = 100           # K
     dt: float = 1e-3
     seed: int = 42
+    lookback: int = 0         # 0 = exact gradient; T > 0 = sensitivities damped by (1 - 1/T)/step
     fixed: dict = field(default_factory=lambda: {k: BASE_PARAMS[k]
                                                  for k in ("gamma0", "F0", "phi")})
 
     def abi(self) -> _lib.AbpAdjointCfg:
-        return _lib.AbpAdjointCfg(self.dt, self.steps, self.window, self.ckpt, self.seed)
+        return _lib.AbpAdjointCfg(self.dt, self.steps, self.window, self.ckpt, self.seed,
+                                  self.lookback)
 
 
 def param_rows(theta: torch.Tensor, cfg: AdjointConfig) -> np.ndarray:

@@ -8,8 +8,9 @@
 // Forward phase: each lane integrates its particle from the workload initial condition and stores
 // its whole state (28 bytes) every K steps. Backward phase: for each segment [jK, (j+1)K) in
 // reverse, the lane restores the checkpoint and recomputes the segment with regenerated Philox
-// noise, leaving sub-checkpoints at absolute multiples of B steps in workspace memory; then, for
-// each sub-window in reverse, it restores the sub-checkpoint, recomputes the sub-window while
+// noise, leaving sub-checkpoints at absolute multiples of B = 16 steps in workspace memory (K is
+// rounded up to a multiple of B); then, for each sub-window in reverse, it restores the
+// sub-checkpoint, recomputes the sub-window while
 // staging the values the reverse step needs (cos and sin of the phase, v, e, sigma*xi) in
 // registers, and runs the adjoint recursion backwards over it. The recomputation reproduces the
 // forward bits exactly (the integrator's state is resumable mid-block), so the result does not
@@ -61,6 +62,8 @@ struct AdjArgs {
     double dt;
     uint32_t k0, k1;
     int32_t n_sets;
+    float rho;        // per-step decay of the adjoint (1 = exact gradient)
+    int32_t vform;    // 1: the loss enters as (1/W) sum of v_n over the window (used with rho < 1)
 };
 
 constexpr int kStage = 8;  // B: steps staged in registers per sub-window (multiple of 4)
@@ -72,11 +75,16 @@ struct AdjLayout {
 
 // Every lane of every wave (also lanes past a set's last particle) owns one slot in the
 // checkpoint planes: N = n_sets * tiles * 64.
+// Checkpoint interval actually used: the requested K rounded up to a multiple of the staging
+// window, so that every segment starts on a sub-window boundary.
+inline int64_t effective_K(int64_t K) { return (K + kStage - 1) / kStage * kStage; }
+
 inline AdjLayout adj_layout(int32_t n_sets, int64_t n, int64_t S, int64_t K)
 {
     AdjLayout L;
+    K = effective_K(K);
     L.n_seg = (S + K - 1) / K;
-    L.n_sub = (K + kStage - 1) / kStage + 1;
+    L.n_sub = K / kStage;
     L.tiles = (n + 63) / 64;
     const size_t N = (size_t)n_sets * (size_t)L.tiles * 64;
     L.rows = 0;
@@ -177,12 +185,94 @@ __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
                     nullptr);
 }
 
-// Staged values of one step for the reverse sweep.
+// Values of one sub-window staged for the reverse sweep: cos and sin of the phase 2 pi (x + phi),
+// v, e (the rounded sums the drift saw) and sigma xi, per step.
 struct Stage {
-    float c, s, v, e, z;
+    float c[kStage], s[kStage], v[kStage], e[kStage], z[kStage];
 };
 
-// Backward phase. lam = dJ_i/dy_{n+1} while step n is reversed.
+// Recompute slot t of a sub-window (absolute step base + t), staging its inputs.
+__device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_t pid, Particle &q,
+                                         float &xb, Noise4 &z, int64_t base, int t, Stage &B)
+{
+    if ((t & 3) == 0)
+        z = noise_block((uint32_t)((base + t) >> 2), pid, s.set, s.k0, s.k1, k.bm);
+    const float xc = xb + q.lx, vc = q.v + q.lv, ec = q.e + q.le;
+    B.c[t] = __builtin_amdgcn_cosf(xc);
+    B.s[t] = __builtin_amdgcn_sinf(xc);
+    B.v[t] = vc;
+    B.e[t] = ec;
+    B.z[t] = z.z[t & 3];
+    step_em(k, q, xb, z.z[t & 3]);
+    if ((t & 3) == 3) {
+        end_block(q);
+        xb = q.xf + k.phi;
+    }
+}
+
+// Adjoint state and the per-window FP32 sums the gradient is assembled from:
+//   A0 = sum lam_v dt cos th      A1 = sum lam_v dt cos 2th     A2 = sum lam_v sigma xi
+//   A3 = sum lam_v dt e v         A4 = sum lam_e dt e v^2       A5 = sum lam_e dt
+//   A6 = sum lam_e dt e
+// (lam = lambda_{n+1}); the parameter constants are applied once at the end (assemble_grad).
+struct Rev {
+    float lx, lv, le;
+    float A[7];
+};
+
+template <int VFORM>
+__device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const Stage &B, int t,
+                                         int64_t n, int64_t wb, float jscale, float invW, float rho,
+                                         Rev &r)
+{
+    if (!VFORM && n + 1 == wb)
+        r.lx -= jscale;  // the window-start position enters J with weight -1/(W dt)
+    const float c = B.c[t], sn = B.s[t], v = B.v[t], e = B.e[t];
+    const float lvdt = r.lv * k.dt, ledt = r.le * k.dt;
+    const float c2 = fmaf(c + c, c, -1.0f);  // cos 2th
+    const float ev = e * v;
+    const float lev = ledt * ev;
+    r.A[0] = fmaf(lvdt, c, r.A[0]);
+    r.A[1] = fmaf(lvdt, c2, r.A[1]);
+    r.A[2] = fmaf(r.lv, B.z[t], r.A[2]);
+    r.A[3] = fmaf(lvdt, ev, r.A[3]);
+    r.A[4] = fmaf(lev, v, r.A[4]);
+    r.A[5] += ledt;
+    r.A[6] = fmaf(ledt, e, r.A[6]);
+    // transpose of the step Jacobian; U'' = -4 pi^2 U0 sin th (1 + 8a cos th)
+    const float nlx = fmaf(-lvdt, rc.m4pi2U0 * (sn * fmaf(rc.eight_a, c, 1.0f)), r.lx);
+    const float nlv =
+        fmaf(-2.0f * k.d2, lev, fmaf(r.lx, k.dt, fmaf(lvdt, fmaf(k.d2, e, -k.g0), r.lv)));
+    const float d2v = k.d2 * v;
+    const float nle = fmaf(lvdt, d2v, fmaf(-ledt, fmaf(d2v, v, k.c), r.le));
+    if (VFORM) {
+        r.lx = rho * nlx;
+        r.lv = fmaf(rho, nlv, n >= wb ? invW : 0.0f);
+        r.le = rho * nle;
+    } else {
+        r.lx = nlx;
+        r.lv = nlv;
+        r.le = nle;
+    }
+}
+
+__device__ __forceinline__ void flush(Rev &r, double (&A64)[7])
+{
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        A64[i] += (double)r.A[i];
+        r.A[i] = 0.0f;
+    }
+}
+
+// Backward phase. lam = dJ_i/dy_{n+1} while step n is reversed. VFORM selects the decayed
+// estimator (see abp_adjoint_cfg.lookback).
+//
+// Within a segment the sub-windows are processed as a software pipeline: while window m is
+// reversed from one staging buffer, window m-1 is recomputed into the other, in the same
+// instruction stream, so the two dependency chains fill each other's latency (the adjoint runs
+// at one wavefront per SIMD for 2^16-particle ensembles).
+template <int VFORM>
 __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
 {
     Lane L;
@@ -195,101 +285,141 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
     const uint32_t pid[1] = {(uint32_t)L.i};
     const int64_t wb = a.S - a.W;
     const float jscale = (float)(1.0 / ((double)a.W * a.dt));
-    float lx = jscale, lv = 0.0f, le = 0.0f;
-    float g32[6] = {0, 0, 0, 0, 0, 0};
-    double g64[6] = {0, 0, 0, 0, 0, 0};
+    const float invW = (float)(1.0 / (double)a.W);
+    const float rho = a.rho;
+    // exact form: J = (x_S - x_{S-W}) / (W dt); decayed form: J = (1/W) sum_{n >= S-W} v_n, which
+    // is the same function of the Euler-Maruyama path, with each v_n's sensitivity damped by rho
+    // per step of look-back
+    Rev r;
+    r.lx = VFORM ? 0.0f : jscale;
+    r.lv = r.le = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        r.A[i] = 0.0f;
+    double A64[7] = {0, 0, 0, 0, 0, 0, 0};
     float *sub = a.sub;
+    const int64_t N = a.N;
 
     const int64_t n_seg = (a.S + a.K - 1) / a.K;
+    // Memory reads are issued one stage ahead of their use (the next segment's checkpoint while
+    // the current segment is reversed, the next sub-checkpoint while the current sub-window is).
+    Particle ck = get_state(a.ckpt + (size_t)(n_seg - 1) * 7 * N, N, L.g);
     for (int64_t j = n_seg - 1; j >= 0; --j) {
-        const int64_t s0 = j * a.K;
+        const int64_t s0 = j * a.K;  // a multiple of kStage
         const int64_t s1 = s0 + a.K < a.S ? s0 + a.K : a.S;
         const int64_t m0 = s0 / kStage, m1 = (s1 - 1) / kStage;
-        // level 1: recompute the segment, leaving a sub-checkpoint at each sub-window start
-        Particle p[1] = {get_state(a.ckpt + (size_t)j * 7 * a.N, a.N, L.g)};
+        // level 1: recompute the segment up to its last sub-window, leaving a sub-checkpoint at
+        // each earlier sub-window start; the last one's start state stays in registers
+        Particle p[1] = {ck};
         int64_t step = s0;
-        for (int64_t m = m0; m <= m1; ++m) {
-            put_state(sub + (size_t)(m - m0) * 7 * a.N, a.N, L.g, p[0]);
-            const int64_t e = (m + 1) * kStage < s1 ? (m + 1) * kStage : s1;
-            advance<0, 1, 1>(k, s, pid, p, step, e);
+        for (int64_t m = m0; m < m1; ++m) {
+            put_state(sub + (size_t)(m - m0) * 7 * N, N, L.g, p[0]);
+            advance<0, 1, 1>(k, s, pid, p, step, (m + 1) * kStage);
         }
-        // level 2: sub-windows in reverse
-        for (int64_t m = m1; m >= m0; --m) {
-            const int64_t base = m * kStage;
-            const int lo = (int)((s0 > base ? s0 : base) - base);
-            const int hi = (int)(((m + 1) * kStage < s1 ? (m + 1) * kStage : s1) - base);
-            Particle q = get_state(sub + (size_t)(m - m0) * 7 * a.N, a.N, L.g);
-            Stage st[kStage];
-            Noise4 z;
+        if (j > 0)
+            ck = get_state(a.ckpt + (size_t)(j - 1) * 7 * N, N, L.g);
+
+        Stage SA, SB;
+        Noise4 z;
+        Particle q = p[0];
+        int64_t m = m1;
+        const int hi1 = (int)(s1 - m1 * kStage);
+        if (hi1 < kStage) {
+            // the run's final sub-window is shorter: recompute and reverse it on its own
             float xb = q.xf + k.phi;
 #pragma unroll
-            for (int t = 0; t < kStage; ++t) {
-                if (t >= lo && t < hi) {
-                    if ((t & 3) == 0 || t == lo)
-                        z = noise_block((uint32_t)((base + t) >> 2), pid[0], s.set, s.k0, s.k1,
-                                        k.sigma);
-                    const float xc = xb + q.lx, vc = q.v + q.lv, ec = q.e + q.le;
-                    st[t].c = __builtin_amdgcn_cosf(xc);
-                    st[t].s = __builtin_amdgcn_sinf(xc);
-                    st[t].v = vc;
-                    st[t].e = ec;
-                    st[t].z = z.z[t & 3];
-                    step_em(k, q, xb, z.z[t & 3]);
-                    if ((t & 3) == 3) {
-                        end_block(q);
-                        xb = q.xf + k.phi;
-                    }
-                }
+            for (int t = 0; t < kStage; ++t)
+                if (t < hi1)
+                    rec_slot(k, s, pid[0], q, xb, z, m1 * kStage, t, SA);
+#pragma unroll
+            for (int t = kStage - 1; t >= 0; --t)
+                if (t < hi1)
+                    rev_slot<VFORM>(k, rc, SA, t, m1 * kStage + t, wb, jscale, invW, rho, r);
+            flush(r, A64);
+            if (m1 == m0)
+                continue;
+            m = m1 - 1;
+            q = get_state(sub + (size_t)(m - m0) * 7 * N, N, L.g);
+        }
+        // prologue: stage window m into SA
+        {
+            float xb = q.xf + k.phi;
+#pragma unroll
+            for (int t = 0; t < kStage; ++t)
+                rec_slot(k, s, pid[0], q, xb, z, m * kStage, t, SA);
+        }
+        Particle nxt;
+        if (m > m0)
+            nxt = get_state(sub + (size_t)(m - 1 - m0) * 7 * N, N, L.g);
+        // steady state, two windows per trip with the staging buffers swapping roles
+        for (;;) {
+            if (m == m0) {
+#pragma unroll
+                for (int t = kStage - 1; t >= 0; --t)
+                    rev_slot<VFORM>(k, rc, SA, t, m * kStage + t, wb, jscale, invW, rho, r);
+                flush(r, A64);
+                break;
             }
+            {
+                q = nxt;
+                if (m - 1 > m0)
+                    nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
+                float xb = q.xf + k.phi;
 #pragma unroll
-            for (int t = kStage - 1; t >= 0; --t) {
-                if (t >= lo && t < hi) {
-                    const int64_t n = base + t;
-                    if (n + 1 == wb)
-                        lx -= jscale;  // the window-start position enters J with weight -1/(W dt)
-                    const float c = st[t].c, sn = st[t].s, v = st[t].v, e = st[t].e;
-                    const float c2 = fmaf(2.0f * c, c, -1.0f);  // cos 2th
-                    const float upp = rc.m4pi2U0 * sn * fmaf(rc.eight_a, c, 1.0f);
-                    const float lvdt = lv * k.dt, ledt = le * k.dt;
-                    const float ev = e * v;
-                    g32[0] = fmaf(-lvdt * rc.two_pi, fmaf(rc.a2, c2, c), g32[0]);
-                    g32[1] = fmaf(-lvdt * rc.four_pi_U0, c2, g32[1]);
-                    g32[2] = fmaf(lv * st[t].z, rc.inv2D, g32[2]);
-                    g32[3] = fmaf(lvdt, ev, fmaf(-ledt * ev, v, g32[3]));
-                    g32[4] += ledt;
-                    g32[5] = fmaf(-ledt, e, g32[5]);
-                    const float nlx = fmaf(-lvdt, upp, lx);
-                    const float nlv = fmaf(lx, k.dt, fmaf(lvdt, fmaf(k.d2, e, -k.g0), lv)) -
-                                      2.0f * k.d2 * ledt * ev;
-                    const float nle = fmaf(lvdt * k.d2, v, fmaf(-ledt, fmaf(k.d2 * v, v, k.c), le));
-                    lx = nlx;
-                    lv = nlv;
-                    le = nle;
-                    if (t == 0) {
-#pragma unroll
-                        for (int r = 0; r < 6; ++r) {
-                            g64[r] += (double)g32[r];
-                            g32[r] = 0.0f;
-                        }
-                    }
+                for (int t = 0; t < kStage; ++t) {
+                    rec_slot(k, s, pid[0], q, xb, z, (m - 1) * kStage, t, SB);
+                    const int u = kStage - 1 - t;
+                    rev_slot<VFORM>(k, rc, SA, u, m * kStage + u, wb, jscale, invW, rho, r);
                 }
+                flush(r, A64);
+                --m;
+            }
+            if (m == m0) {
+#pragma unroll
+                for (int t = kStage - 1; t >= 0; --t)
+                    rev_slot<VFORM>(k, rc, SB, t, m * kStage + t, wb, jscale, invW, rho, r);
+                flush(r, A64);
+                break;
+            }
+            {
+                q = nxt;
+                if (m - 1 > m0)
+                    nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
+                float xb = q.xf + k.phi;
+#pragma unroll
+                for (int t = 0; t < kStage; ++t) {
+                    rec_slot(k, s, pid[0], q, xb, z, (m - 1) * kStage, t, SA);
+                    const int u = kStage - 1 - t;
+                    rev_slot<VFORM>(k, rc, SB, u, m * kStage + u, wb, jscale, invW, rho, r);
+                }
+                flush(r, A64);
+                --m;
             }
         }
     }
+    // dJ/d(U0, a, D, d2, q, c) from the sums (FP64)
+    const double two_pi = 2.0 * 3.14159265358979323846;
+    double g[6];
+    g[0] = -two_pi * (A64[0] + (double)rc.a2 * A64[1]);
+    g[1] = -(double)rc.four_pi_U0 * A64[1];
+    g[2] = (double)rc.inv2D * A64[2];
+    g[3] = A64[3] - A64[4];
+    g[4] = A64[5];
+    g[5] = -A64[6];
     if (a.grad_particles && L.live) {
         double *gp = a.grad_particles + 6 * ((int64_t)L.set * a.n + L.i);
 #pragma unroll
-        for (int r = 0; r < 6; ++r)
-            gp[r] = g64[r];
+        for (int i = 0; i < 6; ++i)
+            gp[i] = g[i];
     }
     // tile partials of the six gradient components (lanes past the end hold zeros)
     if (L.tile * 64 < a.n) {
         double *gp = a.grad_part + 6 * ((int64_t)L.set * a.tiles + L.tile);
 #pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            const double t = wave_sum(L.live ? g64[r] : 0.0);
+        for (int i = 0; i < 6; ++i) {
+            const double t = wave_sum(L.live ? g[i] : 0.0);
             if (L.lane == 0)
-                gp[r] = t;
+                gp[i] = t;
         }
     }
 }
@@ -342,7 +472,7 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         return ABP_E_ARG;
     if (!(cfg->dt > 0.0) || !is_finite(cfg->dt) || cfg->n_steps < 1 ||
         cfg->n_steps > kMaxStepIndex || cfg->window < 1 || cfg->window > cfg->n_steps ||
-        cfg->ckpt_every < 1)
+        cfg->ckpt_every < 1 || cfg->lookback < 0)
         return ABP_E_ARG;
     for (int32_t k = 0; k < n_sets; ++k)
         if (!params_ok(h_params[k]) || !(h_params[k].D > 0.0))
@@ -396,18 +526,22 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
     a.tiles = L.tiles;
     a.S = cfg->n_steps;
     a.W = cfg->window;
-    a.K = cfg->ckpt_every;
+    a.K = effective_K(cfg->ckpt_every);
     a.n_sub = L.n_sub;
     const Stream ks = make_stream(cfg->seed, 0);
     a.k0 = ks.k0;
     a.k1 = ks.k1;
     a.n_sets = n_sets;
+    a.vform = cfg->lookback > 0 ? 1 : 0;
+    a.rho = cfg->lookback > 0 ? (float)(1.0 - 1.0 / (double)cfg->lookback) : 1.0f;
     const int64_t waves = (int64_t)n_sets * L.tiles;
     const unsigned grid = (unsigned)((waves * 64 + 255) / 256);
     if (phase == 0)
         hipLaunchKernelGGL(k_adj_forward, dim3(grid), dim3(256), 0, st, a);
+    else if (a.vform)
+        hipLaunchKernelGGL(k_adj_backward<1>, dim3(grid), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL(k_adj_backward, dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_adj_backward<0>, dim3(grid), dim3(256), 0, st, a);
     if (hipGetLastError() != hipSuccess)
         return ABP_E_HIP;
     hipLaunchKernelGGL(k_adj_finalize, dim3((unsigned)n_sets), dim3(64), 0, st, a, phase);

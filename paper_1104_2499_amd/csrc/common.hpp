@@ -44,7 +44,7 @@ inline Coef make_coef(const abp_params &p, double dt)
     Coef k;
     k.dt = (float)dt;
     k.half_dt = (float)(0.5 * dt);
-    k.sigma = (float)std::sqrt(2.0 * p.D * dt);
+    k.bm = (float)(-2.0 * 0.69314718055994530942 * (2.0 * p.D * dt));
     k.phi = (float)p.phi;
     k.K1 = (float)(2.0 * kPi * p.U0);
     k.B = (float)(8.0 * kPi * p.U0 * p.a);

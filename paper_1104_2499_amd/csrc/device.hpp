@@ -60,20 +60,20 @@ enum : uint32_t { kDomainNoise = 0u, kDomainInit = 1u };
 // One v_alignbit_b32 turns a Philox word w into y = 1 + (w >> 9) 2^-23 in [1, 2) (the word's top
 // 23 bits under the exponent of 1.0). Then u1 = 2 - y1 in (0, 1] exactly, and because v_sin_f32 /
 // v_cos_f32 take their argument in revolutions (period 1), sin(2 pi u2) = v_sin_f32(y2) with
-// u2 = y2 - 1 in [0, 1). v_log_f32 is log2, so -2 ln u1 = -2 ln2 * log2 u1.
+// u2 = y2 - 1 in [0, 1). v_log_f32 is log2, so sigma rho = sqrt(bm * log2 u1) with the
+// wavefront-uniform bm = -2 ln2 sigma^2.
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ float unit_interval_1_2(uint32_t w)
 {
     return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9u));
 }
 
-__device__ __forceinline__ void box_muller_scaled(uint32_t wa, uint32_t wb, float sigma,
-                                                  float &za, float &zb)
+__device__ __forceinline__ void box_muller_scaled(uint32_t wa, uint32_t wb, float bm, float &za,
+                                                  float &zb)
 {
     const float u1 = 2.0f - unit_interval_1_2(wa);
     const float y2 = unit_interval_1_2(wb);
-    const float minus_2ln2 = -1.38629436111989061883f;
-    const float s = sigma * __builtin_amdgcn_sqrtf(minus_2ln2 * __builtin_amdgcn_logf(u1));
+    const float s = __builtin_amdgcn_sqrtf(bm * __builtin_amdgcn_logf(u1));
     za = s * __builtin_amdgcn_cosf(y2);
     zb = s * __builtin_amdgcn_sinf(y2);
 }
@@ -84,12 +84,12 @@ struct Noise4 {
 };
 
 __device__ __forceinline__ Noise4 noise_block(uint32_t blk, uint32_t pid, uint32_t set,
-                                              uint32_t k0, uint32_t k1, float sigma)
+                                              uint32_t k0, uint32_t k1, float bm)
 {
     const Philox4 r = philox4x32_10(blk, pid, set, kDomainNoise, k0, k1);
     Noise4 n;
-    box_muller_scaled(r.w[0], r.w[1], sigma, n.z[0], n.z[1]);
-    box_muller_scaled(r.w[2], r.w[3], sigma, n.z[2], n.z[3]);
+    box_muller_scaled(r.w[0], r.w[1], bm, n.z[0], n.z[1]);
+    box_muller_scaled(r.w[2], r.w[3], bm, n.z[2], n.z[3]);
     return n;
 }
 
@@ -101,7 +101,7 @@ __device__ __forceinline__ Noise4 noise_block(uint32_t blk, uint32_t pid, uint32
 //   f_v = F0 - U'(x) + (d2 e - gamma0) v,   f_e = q - e (c + d2 v^2).
 // ---------------------------------------------------------------------------------------------
 struct Coef {
-    float dt, half_dt, sigma, phi;
+    float dt, half_dt, bm, phi;  // bm = -2 ln2 sigma^2, sigma = sqrt(2 D dt)
     float K1;   // 2 pi U0
     float B;    // 8 pi U0 a
     float FH;   // F0 + 4 pi U0 a
@@ -216,7 +216,7 @@ __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const ui
         const uint32_t j1 = (uint32_t)((stop - n) < (int64_t)(4 - j0) ? j0 + (stop - n) : 4);
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.sigma);
+            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
             const float xb = p[q].xf + k.phi;
             for (uint32_t j = j0; j < j1; ++j)
                 step<SCHEME>(k, p[q], xb, pick(z, j));
@@ -234,7 +234,7 @@ __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const ui
         for (int u = 0; u < UNROLL; ++u) {
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
-                const Noise4 z = noise_block(blk + u, pid[q], s.set, s.k0, s.k1, k.sigma);
+                const Noise4 z = noise_block(blk + u, pid[q], s.set, s.k0, s.k1, k.bm);
                 const float xb = p[q].xf + k.phi;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
@@ -247,7 +247,7 @@ __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const ui
     for (; b < nblk; ++b) {
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.sigma);
+            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
             const float xb = p[q].xf + k.phi;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -262,7 +262,7 @@ __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const ui
         const uint32_t j1 = (uint32_t)(stop - n);
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.sigma);
+            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
             const float xb = p[q].xf + k.phi;
             for (uint32_t j = 0; j < j1; ++j)
                 step<SCHEME>(k, p[q], xb, pick(z, j));

@@ -1,0 +1,101 @@
+"""The paper's own workloads, run on the batched integrator and measured the way Sec. 3 measures.
+
+load_force_curve(): mean drift velocity <v> against the load force F0, one parameter set per F0
+value, all sets in one persistent launch (the use case behind Fig. 2: in Sec. 2 each work item is
+one value of the load force, and all of them run at once). The load power -F0 <v> is returned
+beside it (positive when the particles move against the load).
+
+scaling(): time of one integration call against the number of work items, repeated R times with
+the first repeats discarded (Sec. 3 runs 20 and averages the last 15), for several step counts
+including zero steps; the per-step cost is the slope of a least-squares line of time against the
+step count and the offset its intercept (Sec. 3.2, Fig. 6 methodology). On MI355X the "bands" the
+paper saw on a 9800 GT are expected at multiples of the resident capacity.
+"""
+from __future__ import annotations
+
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import api
+from .workloads import BASE_PARAMS, PARAM_KEYS
+
+
+def load_force_curve(F0, params: dict | None = None, n: int = 4096, steps: int = 100_000,
+                     window: int | None = None, scheme: str = "heun", seed: int = 1,
+                     bins: int = 0, tune=None):
+    """<v>(F0) for each load force in F0 (one set each). Returns dict of numpy arrays."""
+    F0 = np.asarray(F0, dtype=np.float64)
+    base = dict(BASE_PARAMS, **(params or {}))
+    table = np.tile(np.array([base[k] for k in PARAM_KEYS], dtype=np.float64), (F0.size, 1))
+    table[:, PARAM_KEYS.index("F0")] = F0
+    window = steps // 2 if window is None else window
+    r = api.sweep(table, np.full(F0.size, n, np.int32), np.full(F0.size, steps, np.int64),
+                  np.full(F0.size, window, np.int64), scheme=scheme, seed=seed, bins=bins,
+                  tune=tune)
+    return {"F0": F0, "mean_v": r.mean_v, "stderr": r.stderr, "load_power": -F0 * r.mean_v}
+
+
+def _time_call(n: int, steps: int, scheme: str, state, snap, ws, stream) -> float:
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    api.reset_state(state, 1, 0, stream)
+    api.integrate(state, steps, BASE_PARAMS, scheme=scheme, seed=1, win_begin=0, snap=snap, ws=ws,
+                  n_bins=0, stream=stream)
+    api.reduce(ws, n, 0, 1.0, stream)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e3  # microseconds
+
+
+def scaling(sizes, steps=(0, 1000, 10_000), scheme: str = "em", repeats: int = 20,
+            keep: int = 15) -> list[dict]:
+    """Per size: mean and sd of the call time (us) over the last `keep` of `repeats` runs at each
+    step count, and the least-squares per-step cost and offset."""
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n in sizes:
+        state, snap = api.State.empty(n), api.State.empty(n)
+        ws = api.reduce_workspace(n, 0)
+        row = {"n": int(n)}
+        means = []
+        for S in steps:
+            t = [_time_call(n, S, scheme, state, snap, ws, stream) for _ in range(repeats)]
+            t = np.array(t[repeats - keep:])
+            row[f"t{S}_us"] = float(t.mean())
+            row[f"sd{S}_us"] = float(t.std(ddof=1))
+            means.append(t.mean())
+        slope, icpt = np.polyfit(np.array(steps, dtype=np.float64), np.array(means), 1)
+        row["us_per_step"] = float(slope)
+        row["offset_us"] = float(icpt)
+        row["particle_steps_per_s"] = float(n / (slope * 1e-6)) if slope > 0 else None
+        rows.append(row)
+    return rows
+
+
+if __name__ == "__main__":
+    import argparse
+
+    ap = argparse.ArgumentParser(description="load-force curve and scaling experiment")
+    ap.add_argument("what", choices=["force", "scaling"])
+    ap.add_argument("--quick", action="store_true")
+    args = ap.parse_args()
+    if args.what == "force":
+        F0 = np.linspace(-1.0, 0.5, 31)
+        t0 = time.perf_counter()
+        out = load_force_curve(F0, steps=20_000 if args.quick else 100_000)
+        secs = time.perf_counter() - t0
+        for f, v, s, p in zip(out["F0"], out["mean_v"], out["stderr"], out["load_power"]):
+            print(json.dumps({"F0": round(float(f), 4), "mean_v": float(v), "stderr": float(s),
+                              "load_power": float(p)}))
+        print(json.dumps({"seconds": secs}))
+    else:
+        sizes = [2 ** k for k in range(0, 21)]
+        if not args.quick:
+            sizes += list(range(16384, 16384 * 40 + 1, 16384))
+        for row in scaling(sorted(set(sizes)), repeats=8 if args.quick else 20,
+                           keep=5 if args.quick else 15):
+            print(json.dumps(row), flush=True)

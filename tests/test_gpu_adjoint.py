@@ -171,3 +171,22 @@ def test_adjoint_rejects_bad_arguments(gpu):
         adjoint.workspace(1, adjoint.AdjointConfig(n=0, steps=100, window=10, ckpt=10))
     with pytest.raises(api.AbpError, match="ABP_E_ARG"):
         adjoint.forward(adjoint.param_rows(_theta(1), cfg2), cfg2, adjoint.workspace(1, cfg))
+
+
+def test_decayed_estimator_matches_oracle(gpu, orc):
+    """The look-back-damped estimator (lookback = 500 steps) against the FP64 oracle's, at the
+    short horizon and with several sets."""
+    from paper_1104_2499_amd import adjoint
+
+    n_sets, n, S, W = 4, 512, 1000, 400
+    theta = _theta(n_sets, jitter=0.2, seed=8)
+    cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=100, seed=8, lookback=500)
+    rows = adjoint.param_rows(theta, cfg)
+    ws = adjoint.workspace(n_sets, cfg)
+    adjoint.forward(rows, cfg, ws)
+    g = adjoint.backward(rows, cfg, ws, torch.ones(n_sets, dtype=torch.float64)).cpu().numpy()
+    for k in range(n_sets):
+        x0, v0, e0 = orc.init_state(n, 8, k)
+        _, go = orc.adjoint(_params(theta[k]), x0, v0, e0, S, W, seed=8, set_id=k, lookback=500)
+        np.testing.assert_allclose(g[k], go.mean(axis=0), rtol=1e-3,
+                                   atol=1e-6 * np.abs(go.mean(axis=0)).max())

@@ -334,3 +334,30 @@ def test_adjoint_rejects_zero_noise(orc):
     x0, v0, e0 = orc.init_state(4, 1)
     with pytest.raises(ValueError):
         orc.adjoint(dict(D=0.0), x0, v0, e0, 100, 10)
+
+
+def test_decayed_adjoint_limits_and_ou_closed_form(orc):
+    """The decayed estimator: (i) with an effectively infinite look-back it is the exact gradient
+    (for EM the velocity-sum form of J equals the displacement form); (ii) for the free particle
+    (U0 = d2 = 0) v_n = sum_m r^(n-1-m) sigma xi_m with r = 1 - gamma0 dt, and the damping acts
+    once per step between v_(m+1) and v_n, so the decayed
+    dJ/dD = (1/W) sum_{n>=wb} sum_{m<n} (r rho)^(n-1-m) xi_m dsigma/dD in closed form, and J does
+    not depend on q or c."""
+    n, S, W = 16, 600, 200
+    x0, v0, e0 = orc.init_state(n, 4)
+    J, g = orc.adjoint(None, x0, v0, e0, S, W, seed=4)
+    J2, g2 = orc.adjoint(None, x0, v0, e0, S, W, seed=4, lookback=10**15)
+    np.testing.assert_allclose(g2, g, rtol=1e-6, atol=1e-9 * np.abs(g).max())
+    D, T, dt = 0.3, 50, 1e-3
+    p = dict(U0=0.0, d2=0.0, D=D, gamma0=1.0)
+    _, gd = orc.adjoint(p, x0, v0, e0, S, W, seed=4, lookback=T)
+    r, rho = 1 - dt, 1 - 1 / T
+    dsig = np.sqrt(dt / (2 * D))
+    for i in range(n):
+        xi = orc.normals(4, i, 0, 0, S)
+        total = 0.0
+        for k in range(S - W, S):
+            m = np.arange(k)
+            total += np.sum((r * rho) ** (k - 1 - m) * xi[m]) * dsig
+        assert gd[i, 2] == pytest.approx(total / W, rel=1e-9, abs=1e-12)
+        assert abs(gd[i, 4]) < 1e-15 and abs(gd[i, 5]) < 1e-15
