@@ -195,8 +195,8 @@ size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set, int64_t n_
  * checkpoints in d_ws, and write d_loss[k] = L_k = (1/n) sum_i (x_S - x_{S-W}) / (W dt), the same
  * value abp_integrate + abp_reduce give for that set alone with set_id = k.
  * phase 1 (backward): with d_ws left by phase 0 for identical arguments, write
- * d_grad[6k + j] = d_gloss[k] * dL_k/dtheta_j, theta = (U0, a, D, d2, q, c), and, if
- * d_grad_particles is non-NULL, d_grad_particles[6 (k n + i) + j] = dJ_i/dtheta_j of particle i of
+ * d_grad[8k + j] = d_gloss[k] * dL_k/dtheta_j, theta = (U0, a, D, d2, q, c, gamma0, F0), and,
+ * if d_grad_particles is non-NULL, d_grad_particles[8 (k n + i) + j] = dJ_i/dtheta_j of particle i of
  * set k (unscaled; used for per-particle checks and gradient statistics).
  * h_params is read during the call (its per-set constants are staged into d_ws, after which the
  * call waits for the stream to drain); the kernels then run asynchronously on `stream`. */

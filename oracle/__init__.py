@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 PARAM_KEYS = ("U0", "a", "phi", "gamma0", "F0", "d2", "q", "c", "D")
 DEFAULTS = dict(U0=1.0, a=0.25, phi=0.0, gamma0=1.0, F0=0.0, d2=1.0, q=1.0, c=0.1, D=0.1)
-GRAD_KEYS = ("U0", "a", "D", "d2", "q", "c")
+GRAD_KEYS = ("U0", "a", "D", "d2", "q", "c", "gamma0", "F0")
 EM, HEUN = 0, 1
 
 
@@ -67,11 +67,11 @@ def _load():
     lib.orc_integrate.restype = ctypes.c_int
     lib.orc_reduce.argtypes = [i64, vp, vp, f64, i32, vp, vp]
     lib.orc_rk4.argtypes = [P(_Params), f64, i64, i64, vp, vp, vp]
-    lib.orc_adjoint.argtypes = [P(_Params), f64, i64, i64, u64, u32, i64, vp, vp, vp, vp, vp, vp,
-                                f64, i64]
+    lib.orc_adjoint.argtypes = [P(_Params), ctypes.c_int, f64, i64, i64, u64, u32, i64, vp, vp,
+                                vp, vp, vp, vp, f64, i64]
     lib.orc_adjoint.restype = ctypes.c_int
-    lib.orc_complex_step.argtypes = [P(_Params), ctypes.c_int, f64, f64, i64, i64, u64, u32, i64,
-                                     vp, vp, vp, vp, vp, vp]
+    lib.orc_complex_step.argtypes = [P(_Params), ctypes.c_int, ctypes.c_int, f64, f64, i64, i64,
+                                     u64, u32, i64, vp, vp, vp, vp, vp, vp]
     lib.orc_complex_step.restype = ctypes.c_int
     lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -182,29 +182,33 @@ def rk4(params: dict | None, x, v, e, n_steps: int, dt: float):
 
 
 def adjoint(params: dict | None, x0, v0, e0, n_steps: int, window: int, dt: float = 1e-3,
-            seed: int = 42, set_id: int = 0, ids=None, eps: float = 0.0, lookback: int = 0):
-    """Per-particle J_i = (x_S - x_{S-W})/(W dt) and dJ_i/d(U0, a, D, d2, q, c) [n, 6] by the
-    discrete adjoint of Euler-Maruyama with the full trajectory stored. eps != 0 linearises around
-    the path perturbed by the rounding-sensitivity model (a conditioning probe). lookback = T > 0
-    gives the decayed estimator (each window velocity's sensitivity damped by 1 - 1/T per step)."""
+            seed: int = 42, set_id: int = 0, ids=None, eps: float = 0.0, lookback: int = 0,
+            scheme: int = EM):
+    """Per-particle J_i = (x_S - x_{S-W})/(W dt) and dJ_i/d(U0, a, D, d2, q, c, gamma0, F0)
+    [n, 8] by the discrete adjoint of the scheme (EM or Heun) with the full trajectory stored.
+    eps != 0 linearises around the path perturbed by the rounding-sensitivity model (a
+    conditioning probe). lookback = T > 0 (EM only) gives the decayed estimator (each window
+    velocity's sensitivity damped by 1 - 1/T per step)."""
     x0 = np.ascontiguousarray(x0, dtype=np.float64)
     v0 = np.ascontiguousarray(v0, dtype=np.float64)
     e0 = np.ascontiguousarray(e0, dtype=np.float64)
     n = x0.shape[0]
-    J = np.empty(n); g = np.empty((n, 6))
+    J = np.empty(n); g = np.empty((n, len(GRAD_KEYS)))
     ids = _ids(ids, n)
     p = _params(params)
-    rc = _load().orc_adjoint(ctypes.byref(p), dt, n_steps, window, seed, set_id, n, _ptr(ids),
-                             _ptr(x0), _ptr(v0), _ptr(e0), _ptr(J), _ptr(g), float(eps),
-                             int(lookback))
+    rc = _load().orc_adjoint(ctypes.byref(p), scheme, dt, n_steps, window, seed, set_id, n,
+                             _ptr(ids), _ptr(x0), _ptr(v0), _ptr(e0), _ptr(J), _ptr(g),
+                             float(eps), int(lookback))
     if rc != 0:
         raise ValueError(f"oracle adjoint failed (rc={rc})")
     return J, g
 
 
 def complex_step(params: dict | None, which: int, x0, v0, e0, n_steps: int, window: int,
-                 dt: float = 1e-3, seed: int = 42, set_id: int = 0, ids=None, h: float = 1e-30):
-    """Per-particle dJ_i/dtheta_which by the complex-step method; also returns Re J_i."""
+                 dt: float = 1e-3, seed: int = 42, set_id: int = 0, ids=None, h: float = 1e-30,
+                 scheme: int = EM):
+    """Per-particle dJ_i/dtheta_which (GRAD_KEYS order) by the complex-step method; also
+    returns Re J_i."""
     x0 = np.ascontiguousarray(x0, dtype=np.float64)
     v0 = np.ascontiguousarray(v0, dtype=np.float64)
     e0 = np.ascontiguousarray(e0, dtype=np.float64)
@@ -212,8 +216,9 @@ def complex_step(params: dict | None, which: int, x0, v0, e0, n_steps: int, wind
     dJ = np.empty(n); Jre = np.empty(n)
     ids = _ids(ids, n)
     p = _params(params)
-    rc = _load().orc_complex_step(ctypes.byref(p), which, h, dt, n_steps, window, seed, set_id, n,
-                                  _ptr(ids), _ptr(x0), _ptr(v0), _ptr(e0), _ptr(dJ), _ptr(Jre))
+    rc = _load().orc_complex_step(ctypes.byref(p), scheme, which, h, dt, n_steps, window, seed,
+                                  set_id, n, _ptr(ids), _ptr(x0), _ptr(v0), _ptr(e0), _ptr(dJ),
+                                  _ptr(Jre))
     if rc != 0:
         raise ValueError("oracle complex step rejected its arguments")
     return dJ, Jre

@@ -286,21 +286,64 @@ void orc_rk4(const orc_params *p, double dt, int64_t n_steps, int64_t n, double 
 }
 
 /* ---------------------------------------------------------------------------------------------
- * Discrete adjoint of the Euler-Maruyama map for the per-particle window mean velocity
+ * Discrete adjoint of the integrator map for the per-particle window mean velocity
  *   J_i = (x_S - x_{S-W}) / (W dt).
- * The whole trajectory of a particle is stored (no checkpoints); lambda_n = dJ/dy_n is carried
- * from n = S down to 0 through the transposed Jacobian of the step, and the explicit parameter
- * derivatives of each step are accumulated. Gradient order: (U0, a, D, d2, q, c).
+ * The whole trajectory of a particle is stored (no checkpoints); lambda_k = dJ/dy_k is carried
+ * from k = S down to 0 through the transposed Jacobian of the step, and the explicit parameter
+ * derivatives of each step are accumulated. Gradient order:
+ *   (U0, a, D, d2, q, c, gamma0, F0).
+ *
+ * With f the drift of Eqs. (1)-(2), J_f its Jacobian, f_th its parameter derivative and
+ * g xi = (0, sigma xi, 0) the noise increment (sigma = sqrt(2 D dt)):
+ *   EM    y' = y + f(y) dt + g xi
+ *         lambda = lambda' + dt J_f(y)^T lambda'
+ *         grad  += dt f_th(y)^T lambda' + lambda'_v xi dsigma/dtheta
+ *   Heun  y~ = y + f(y) dt + g xi,   y' = y + (f(y) + f(y~)) dt/2 + g xi
+ *         mu = J_f(y~)^T lambda',  nu = lambda' + dt mu
+ *         lambda = lambda' + dt/2 (mu + J_f(y)^T nu)
+ *         grad  += dt/2 f_th(y~)^T lambda' + dt/2 f_th(y)^T nu + (lambda'_v + dt/2 mu_v) xi dsigma/dth
+ *
  * eps != 0 records the forward path under the rounding-sensitivity model (see perturb) and
  * linearises around that path, which measures how well-conditioned each particle's gradient is.
- * lookback = T > 0 computes the decayed estimator described at the recursion below.
+ * lookback = T > 0 (Euler-Maruyama only) computes the decayed estimator: J is written as
+ * (1/W) sum of v_k for k >= wb (the same function of the EM path), each v_k's sensitivity
+ * carried back with an extra factor rho = 1 - 1/T per step.
  * Returns -1 on bad input (D must be > 0 since dsigma/dD is singular at D = 0).
  * ------------------------------------------------------------------------------------------- */
-int orc_adjoint(const orc_params *p, double dt, int64_t n_steps, int64_t window, uint64_t seed,
-                uint32_t set, int64_t n, const uint32_t *ids, const double *x0, const double *v0,
-                const double *e0, double *J, double *grad, double eps, int64_t lookback)
+enum { NGRAD = 8 };
+
+/* J_f(y)^T w */
+static void drift_jac_t(const orc_params *p, const double y[3], const double w[3], double out[3])
 {
-    if (!(dt > 0.0) || n_steps < 1 || window < 1 || window > n_steps || !(p->D > 0.0))
+    const double x = y[0], v = y[1], e = y[2];
+    out[0] = -d2U(p, x) * w[1];
+    out[1] = w[0] + (p->d2 * e - p->gamma0) * w[1] - 2.0 * p->d2 * e * v * w[2];
+    out[2] = p->d2 * v * w[1] - (p->c + p->d2 * v * v) * w[2];
+}
+
+/* g[j] += scale * f_theta_j(y)^T w for the drift-borne parameters (all but D) */
+static void add_drift_param_grad(const orc_params *p, const double y[3], const double w[3],
+                                 double scale, double g[NGRAD])
+{
+    const double x = y[0], v = y[1], e = y[2];
+    const double th = 2.0 * ORC_PI * (x + p->phi);
+    g[0] += scale * w[1] * (-2.0 * ORC_PI * (cos(th) + 2.0 * p->a * cos(2.0 * th)));
+    g[1] += scale * w[1] * (-4.0 * ORC_PI * p->U0 * cos(2.0 * th));
+    g[3] += scale * (w[1] * e * v - w[2] * e * v * v);
+    g[4] += scale * w[2];
+    g[5] += scale * w[2] * (-e);
+    g[6] += scale * w[1] * (-v);
+    g[7] += scale * w[1];
+}
+
+int orc_adjoint(const orc_params *p, int scheme, double dt, int64_t n_steps, int64_t window,
+                uint64_t seed, uint32_t set, int64_t n, const uint32_t *ids, const double *x0,
+                const double *v0, const double *e0, double *J, double *grad, double eps,
+                int64_t lookback)
+{
+    if (!(dt > 0.0) || n_steps < 1 || window < 1 || window > n_steps || !(p->D > 0.0) ||
+        (scheme != ORC_EM && scheme != ORC_HEUN) || lookback < 0 ||
+        (lookback > 0 && scheme != ORC_EM))
         return -1;
     const double sig = sqrt(2.0 * p->D * dt);
     const double dsig_dD = sqrt(dt / (2.0 * p->D));
@@ -310,12 +353,10 @@ int orc_adjoint(const orc_params *p, double dt, int64_t n_steps, int64_t window,
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < n; ++i) {
         uint32_t pid = ids ? ids[i] : (uint32_t)i;
-        double *tx = malloc(sizeof(double) * (size_t)(n_steps + 1));
-        double *tv = malloc(sizeof(double) * (size_t)(n_steps + 1));
-        double *te = malloc(sizeof(double) * (size_t)(n_steps + 1));
+        double *ty = malloc(sizeof(double) * 3 * (size_t)(n_steps + 1));
         double *tz = malloc(sizeof(double) * (size_t)n_steps);
-        if (!tx || !tv || !te || !tz) {
-            free(tx); free(tv); free(te); free(tz);
+        if (!ty || !tz) {
+            free(ty); free(tz);
 #pragma omp atomic write
             failed = 1;
             continue;
@@ -323,104 +364,123 @@ int orc_adjoint(const orc_params *p, double dt, int64_t n_steps, int64_t window,
         orc_normals(seed, pid, set, 0, n_steps, tz);
         double y[3] = {x0[i], v0[i], e0[i]};
         for (int64_t k = 0; k < n_steps; ++k) {
-            tx[k] = y[0]; tv[k] = y[1]; te[k] = y[2];
-            one_step(p, ORC_EM, dt, sig, tz[k], y);
+            memcpy(ty + 3 * k, y, sizeof y);
+            one_step(p, scheme, dt, sig, tz[k], y);
             if (eps != 0.0)
                 perturb(seed, pid, set, k, eps, y);
         }
-        tx[n_steps] = y[0]; tv[n_steps] = y[1]; te[n_steps] = y[2];
-        J[i] = (tx[n_steps] - tx[wb]) * jscale;
+        memcpy(ty + 3 * n_steps, y, sizeof y);
+        J[i] = (ty[3 * n_steps] - ty[3 * wb]) * jscale;
 
-        /* Exact gradient (lookback = 0): J = (x_S - x_wb) s with s = 1/(W dt) enters lambda at
-         * x_S and x_wb. Decayed estimator (lookback = T > 0): J is written as (1/W) sum of v_k for
-         * k >= wb (the same function of the EM path), each v_k's sensitivity carried back with an
-         * extra factor rho = 1 - 1/T per step. */
         const int vform = lookback > 0;
         const double rho = vform ? 1.0 - 1.0 / (double)lookback : 1.0;
-        double lx = vform ? 0.0 : jscale, lv = 0.0, le = 0.0;
-        double g[6] = {0, 0, 0, 0, 0, 0};
+        double lam[3] = {vform ? 0.0 : jscale, 0.0, 0.0};
+        double g[NGRAD] = {0};
         for (int64_t k = n_steps - 1; k >= 0; --k) {
-            /* lambda currently holds dJ/dy_{k+1}; the snapshot term enters at index wb. */
+            /* lam holds dJ/dy_{k+1}; the window-start position enters at index wb */
             if (k + 1 == wb && !vform)
-                lx -= jscale;
-            double xk = tx[k], vk = tv[k], ek = te[k];
-            double th = 2.0 * ORC_PI * (xk + p->phi);
-            /* explicit parameter derivatives of y_{k+1} (only v and e depend on parameters) */
-            g[0] += lv * (-2.0 * ORC_PI * (cos(th) + 2.0 * p->a * cos(2.0 * th)) * dt);
-            g[1] += lv * (-4.0 * ORC_PI * p->U0 * cos(2.0 * th) * dt);
-            g[2] += lv * (tz[k] * dsig_dD);
-            g[3] += lv * (ek * vk * dt) + le * (-ek * vk * vk * dt);
-            g[4] += le * dt;
-            g[5] += le * (-ek * dt);
-            /* transpose of the step Jacobian */
-            double nlx = lx + lv * (-d2U(p, xk) * dt);
-            double nlv = lx * dt + lv * (1.0 + (p->d2 * ek - p->gamma0) * dt) +
-                         le * (-2.0 * p->d2 * ek * vk * dt);
-            double nle = lv * (p->d2 * vk * dt) + le * (1.0 - (p->c + p->d2 * vk * vk) * dt);
-            if (vform) {
-                lx = rho * nlx;
-                lv = rho * nlv + (k >= wb ? 1.0 / (double)window : 0.0);
-                le = rho * nle;
+                lam[0] -= jscale;
+            const double *yk = ty + 3 * k;
+            double nl[3], jt[3];
+            if (scheme == ORC_EM) {
+                add_drift_param_grad(p, yk, lam, dt, g);
+                g[2] += lam[1] * tz[k] * dsig_dD;
+                drift_jac_t(p, yk, lam, jt);
+                for (int d = 0; d < 3; ++d)
+                    nl[d] = lam[d] + dt * jt[d];
             } else {
-                lx = nlx; lv = nlv; le = nle;
+                double f[3], yp[3];
+                drift(p, yk[0], yk[1], yk[2], f);
+                yp[0] = yk[0] + f[0] * dt;
+                yp[1] = yk[1] + f[1] * dt + sig * tz[k];
+                yp[2] = yk[2] + f[2] * dt;
+                double mu[3], nu[3];
+                drift_jac_t(p, yp, lam, mu);
+                for (int d = 0; d < 3; ++d)
+                    nu[d] = lam[d] + dt * mu[d];
+                add_drift_param_grad(p, yp, lam, 0.5 * dt, g);
+                add_drift_param_grad(p, yk, nu, 0.5 * dt, g);
+                g[2] += (lam[1] + 0.5 * dt * mu[1]) * tz[k] * dsig_dD;
+                drift_jac_t(p, yk, nu, jt);
+                for (int d = 0; d < 3; ++d)
+                    nl[d] = lam[d] + 0.5 * dt * (mu[d] + jt[d]);
+            }
+            if (vform) {
+                lam[0] = rho * nl[0];
+                lam[1] = rho * nl[1] + (k >= wb ? 1.0 / (double)window : 0.0);
+                lam[2] = rho * nl[2];
+            } else {
+                memcpy(lam, nl, sizeof nl);
             }
         }
-        if (wb == 0 && !vform)
-            lx -= jscale;
-        (void)lx;
-        for (int j = 0; j < 6; ++j)
-            grad[6 * i + j] = g[j];
-        free(tx); free(tv); free(te); free(tz);
+        for (int j = 0; j < NGRAD; ++j)
+            grad[NGRAD * i + j] = g[j];
+        free(ty); free(tz);
     }
     return failed ? -2 : 0;
 }
 
 /* ---------------------------------------------------------------------------------------------
- * Complex-step derivative (Squire & Trapp 1998): the same Euler-Maruyama recursion run in complex
- * arithmetic with parameter `which` (0..5 = U0, a, D, d2, q, c) shifted by i*h. For an analytic
+ * Complex-step derivative (Squire & Trapp 1998): the same integrator run in complex arithmetic
+ * with parameter `which` (0..7 = U0, a, D, d2, q, c, gamma0, F0) shifted by i*h. For an analytic
  * recursion Im(J(theta + i h))/h equals dJ/dtheta up to rounding, with no subtractive
- * cancellation. Forward-mode and independent of the adjoint above; used to pin it.
+ * cancellation. Forward mode and independent of the adjoint above; used to pin it.
  * ------------------------------------------------------------------------------------------- */
-int orc_complex_step(const orc_params *p, int which, double h, double dt, int64_t n_steps,
-                     int64_t window, uint64_t seed, uint32_t set, int64_t n, const uint32_t *ids,
-                     const double *x0, const double *v0, const double *e0, double *dJ,
-                     double *J_re)
+typedef struct {
+    double complex U0, a, D, d2, q, c, gamma0, F0;
+} cparams;
+
+static void cdrift(const cparams *cp, double phi, double complex x, double complex v,
+                   double complex e, double complex f[3])
 {
-    if (which < 0 || which > 5 || !(dt > 0.0) || n_steps < 1 || window < 1 || window > n_steps)
+    double complex th = 2.0 * ORC_PI * (x + phi);
+    double complex dUx = 2.0 * ORC_PI * cp->U0 * (ccos(th) + 2.0 * cp->a * ccos(2.0 * th));
+    f[0] = v;
+    f[1] = cp->F0 - cp->gamma0 * v + cp->d2 * e * v - dUx;
+    f[2] = cp->q - cp->c * e - cp->d2 * e * v * v;
+}
+
+int orc_complex_step(const orc_params *p, int scheme, int which, double h, double dt,
+                     int64_t n_steps, int64_t window, uint64_t seed, uint32_t set, int64_t n,
+                     const uint32_t *ids, const double *x0, const double *v0, const double *e0,
+                     double *dJ, double *J_re)
+{
+    if (which < 0 || which >= NGRAD || !(dt > 0.0) || n_steps < 1 || window < 1 ||
+        window > n_steps || (scheme != ORC_EM && scheme != ORC_HEUN))
         return -1;
-    double complex U0 = p->U0, a = p->a, D = p->D, d2 = p->d2, q = p->q, c = p->c;
-    switch (which) {
-    case 0: U0 += I * h; break;
-    case 1: a += I * h; break;
-    case 2: D += I * h; break;
-    case 3: d2 += I * h; break;
-    case 4: q += I * h; break;
-    default: c += I * h; break;
-    }
-    const double complex sig = csqrt(2.0 * D * dt);
+    cparams cp = {p->U0, p->a, p->D, p->d2, p->q, p->c, p->gamma0, p->F0};
+    double complex *field[NGRAD] = {&cp.U0, &cp.a, &cp.D, &cp.d2, &cp.q, &cp.c, &cp.gamma0, &cp.F0};
+    *field[which] += I * h;
+    const double complex sig = csqrt(2.0 * cp.D * dt);
     const int64_t wb = n_steps - window;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < n; ++i) {
         uint32_t pid = ids ? ids[i] : (uint32_t)i;
-        double complex x = x0[i], v = v0[i], e = e0[i], xs = x0[i];
+        double complex y[3] = {x0[i], v0[i], e0[i]}, xs = x0[i];
         double z[4];
         for (int64_t k = 0; k < n_steps; ++k) {
             if (k == wb)
-                xs = x;
+                xs = y[0];
             if (k % 4 == 0)
                 normals4(seed, pid, set, (uint32_t)(k / 4), z);
-            double complex th = 2.0 * ORC_PI * (x + p->phi);
-            double complex dUx = 2.0 * ORC_PI * U0 * (ccos(th) + 2.0 * a * ccos(2.0 * th));
-            double complex fv = p->F0 - p->gamma0 * v + d2 * e * v - dUx;
-            double complex fe = q - c * e - d2 * e * v * v;
-            double complex nx = x + v * dt;
-            double complex nv = v + fv * dt + sig * z[k % 4];
-            double complex ne = e + fe * dt;
-            x = nx; v = nv; e = ne;
+            double complex f[3], yp[3];
+            cdrift(&cp, p->phi, y[0], y[1], y[2], f);
+            yp[0] = y[0] + f[0] * dt;
+            yp[1] = y[1] + f[1] * dt + sig * z[k % 4];
+            yp[2] = y[2] + f[2] * dt;
+            if (scheme == ORC_EM) {
+                y[0] = yp[0]; y[1] = yp[1]; y[2] = yp[2];
+            } else {
+                double complex fp[3];
+                cdrift(&cp, p->phi, yp[0], yp[1], yp[2], fp);
+                y[0] = y[0] + 0.5 * (f[0] + fp[0]) * dt;
+                y[1] = y[1] + 0.5 * (f[1] + fp[1]) * dt + sig * z[k % 4];
+                y[2] = y[2] + 0.5 * (f[2] + fp[2]) * dt;
+            }
         }
         if (wb == n_steps)
-            xs = x;
-        double complex Jc = (x - xs) / ((double)window * dt);
+            xs = y[0];
+        double complex Jc = (y[0] - xs) / ((double)window * dt);
         dJ[i] = cimag(Jc) / h;
         if (J_re)
             J_re[i] = creal(Jc);

@@ -1,7 +1,7 @@
 """Pathwise gradients of the window mean velocity as a torch.autograd.Function.
 
-theta [n_sets, 6] float64 holds (U0, a, D, d2, q, c) per parameter set; the other parameters of
-Eqs. (1)-(3) (gamma0, F0, phi) are fixed by the config. The forward pass runs abp_adjoint phase 0
+theta [n_sets, 8] float64 holds (U0, a, D, d2, q, c, gamma0, F0) per parameter set; the phase phi
+of the potential, Eq. (4), is fixed by the config. The forward pass runs abp_adjoint phase 0
 (integrate with checkpoints, loss L_k = mean velocity of set k over the last W steps); backward
 runs phase 1 (checkpointed discrete adjoint with regenerated noise). All arithmetic is in the HIP
 library; torch provides the buffers and the stream.
@@ -18,7 +18,7 @@ from . import _lib
 from .api import _stream, check
 from .workloads import BASE_PARAMS, PARAM_KEYS
 
-GRAD_KEYS = ("U0", "a", "D", "d2", "q", "c")
+GRAD_KEYS = ("U0", "a", "D", "d2", "q", "c", "gamma0", "F0")
 
 
 @dataclass
@@ -30,8 +30,7 @@ class AdjointConfig:
     dt: float = 1e-3
     seed: int = 42
     lookback: int = 0         # 0 = exact gradient; T > 0 = sensitivities damped by (1 - 1/T)/step
-    fixed: dict = field(default_factory=lambda: {k: BASE_PARAMS[k]
-                                                 for k in ("gamma0", "F0", "phi")})
+    fixed: dict = field(default_factory=lambda: {"phi": BASE_PARAMS["phi"]})
 
     def abi(self) -> _lib.AbpAdjointCfg:
         return _lib.AbpAdjointCfg(self.dt, self.steps, self.window, self.ckpt, self.seed,
@@ -39,10 +38,10 @@ class AdjointConfig:
 
 
 def param_rows(theta: torch.Tensor, cfg: AdjointConfig) -> np.ndarray:
-    """[n_sets, 9] float64 host rows in PARAM_KEYS order from theta [n_sets, 6]."""
+    """[n_sets, 9] float64 host rows in PARAM_KEYS order from theta [n_sets, 8]."""
     th = theta.detach().to("cpu", torch.float64).numpy()
     if th.ndim != 2 or th.shape[1] != len(GRAD_KEYS):
-        raise ValueError("theta must be [n_sets, 6] = (U0, a, D, d2, q, c)")
+        raise ValueError("theta must be [n_sets, 8] = (U0, a, D, d2, q, c, gamma0, F0)")
     rows = np.empty((th.shape[0], len(PARAM_KEYS)), dtype=np.float64)
     col = {k: i for i, k in enumerate(PARAM_KEYS)}
     base = dict(BASE_PARAMS, **cfg.fixed)
@@ -75,8 +74,9 @@ def backward(rows: np.ndarray, cfg: AdjointConfig, ws: torch.Tensor, gloss: torc
              per_particle: bool = False, stream=None):
     n_sets = rows.shape[0]
     gloss = gloss.detach().to(ws.device, torch.float64).contiguous()
-    grad = torch.empty((n_sets, 6), dtype=torch.float64, device=ws.device)
-    gp = (torch.empty((n_sets, cfg.n, 6), dtype=torch.float64, device=ws.device)
+    ng = len(GRAD_KEYS)
+    grad = torch.empty((n_sets, ng), dtype=torch.float64, device=ws.device)
+    gp = (torch.empty((n_sets, cfg.n, ng), dtype=torch.float64, device=ws.device)
           if per_particle else None)
     c = cfg.abi()
     check(_lib.load().abp_adjoint(1, n_sets, rows.ctypes.data, cfg.n, ctypes.byref(c),
@@ -89,7 +89,7 @@ def backward(rows: np.ndarray, cfg: AdjointConfig, ws: torch.Tensor, gloss: torc
 
 
 class MeanVelocity(torch.autograd.Function):
-    """L = MeanVelocity.apply(theta, cfg): theta [n_sets, 6] -> L [n_sets] (float64, cuda)."""
+    """L = MeanVelocity.apply(theta, cfg): theta [n_sets, 8] -> L [n_sets] (float64, cuda)."""
 
     @staticmethod
     def forward(ctx, theta: torch.Tensor, cfg: AdjointConfig):

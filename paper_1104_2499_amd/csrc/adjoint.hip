@@ -3,7 +3,7 @@
 //
 // Loss of set k: L_k = (1/N) sum_i J_i, J_i = (x_S - x_{S-W}) / (W dt), i.e. the mean drift
 // velocity that abp_integrate reports for the same set (bit for bit). Gradient order:
-// (U0, a, D, d2, q, c).
+// (U0, a, D, d2, q, c, gamma0, F0).
 //
 // Forward phase: each lane integrates its particle from the workload initial condition and stores
 // its whole state (28 bytes) every K steps. Backward phase: for each segment [jK, (j+1)K) in
@@ -20,7 +20,7 @@
 //
 // Workspace layout (abp_adjoint_workspace_bytes):
 //   AdjRow rows[n_sets] | float ckpt[n_seg][7][N] | float sub[n_sub][7][N] |
-//   double loss_part[n_sets][tiles][2] | double grad_part[n_sets][tiles][6]
+//   double loss_part[n_sets][tiles][2] | double grad_part[n_sets][tiles][8]
 // (N = n_sets * tiles * 64 checkpoint slots: one per lane, also past a set's last particle)
 #include <vector>
 
@@ -49,11 +49,11 @@ struct AdjArgs {
     float *ckpt;        // [n_seg][7][N]
     float *sub;         // [n_sub][7][N]
     double *loss_part;  // [n_sets][tiles][2]
-    double *grad_part;  // [n_sets][tiles][6]
+    double *grad_part;  // [n_sets][tiles][8]
     const double *gloss;
     double *loss;
     double *grad;
-    double *grad_particles;  // optional [n_sets][n][6]: dJ_i/dtheta per particle
+    double *grad_particles;  // optional [n_sets][n][8]: dJ_i/dtheta per particle
     int64_t n;          // particles per set
     int64_t N;          // checkpoint slots (64 per tile)
     int64_t tiles;      // tiles per set
@@ -66,7 +66,8 @@ struct AdjArgs {
     int32_t vform;    // 1: the loss enters as (1/W) sum of v_n over the window (used with rho < 1)
 };
 
-constexpr int kStage = 8;  // B: steps staged in registers per sub-window (multiple of 4)
+constexpr int kStage = 16;  // B: steps staged in registers per sub-window (multiple of 4)
+constexpr int kGrad = 8;    // gradient components: U0, a, D, d2, q, c, gamma0, F0
 
 struct AdjLayout {
     size_t rows, ckpt, sub, loss, grad, total;
@@ -92,7 +93,7 @@ inline AdjLayout adj_layout(int32_t n_sets, int64_t n, int64_t S, int64_t K)
     L.sub = align_up(L.ckpt + sizeof(float) * 7 * N * (size_t)L.n_seg, 256);
     L.loss = align_up(L.sub + sizeof(float) * 7 * N * (size_t)L.n_sub, 256);
     L.grad = align_up(L.loss + sizeof(double) * 2 * (size_t)n_sets * (size_t)L.tiles, 256);
-    L.total = align_up(L.grad + sizeof(double) * 6 * (size_t)n_sets * (size_t)L.tiles, 256);
+    L.total = align_up(L.grad + sizeof(double) * kGrad * (size_t)n_sets * (size_t)L.tiles, 256);
     return L;
 }
 
@@ -213,11 +214,13 @@ __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_
 // Adjoint state and the per-window FP32 sums the gradient is assembled from:
 //   A0 = sum lam_v dt cos th      A1 = sum lam_v dt cos 2th     A2 = sum lam_v sigma xi
 //   A3 = sum lam_v dt e v         A4 = sum lam_e dt e v^2       A5 = sum lam_e dt
-//   A6 = sum lam_e dt e
-// (lam = lambda_{n+1}); the parameter constants are applied once at the end (assemble_grad).
+//   A6 = sum lam_e dt e           A7 = sum lam_v dt v           A8 = sum lam_v dt
+// (lam = lambda_{n+1}); the parameter constants are applied once at the end.
+constexpr int kSums = 9;
+
 struct Rev {
     float lx, lv, le;
-    float A[7];
+    float A[kSums];
 };
 
 template <int VFORM>
@@ -239,6 +242,8 @@ __device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const
     r.A[4] = fmaf(lev, v, r.A[4]);
     r.A[5] += ledt;
     r.A[6] = fmaf(ledt, e, r.A[6]);
+    r.A[7] = fmaf(lvdt, v, r.A[7]);
+    r.A[8] += lvdt;
     // transpose of the step Jacobian; U'' = -4 pi^2 U0 sin th (1 + 8a cos th)
     const float nlx = fmaf(-lvdt, rc.m4pi2U0 * (sn * fmaf(rc.eight_a, c, 1.0f)), r.lx);
     const float nlv =
@@ -256,10 +261,10 @@ __device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const
     }
 }
 
-__device__ __forceinline__ void flush(Rev &r, double (&A64)[7])
+__device__ __forceinline__ void flush(Rev &r, double (&A64)[kSums])
 {
 #pragma unroll
-    for (int i = 0; i < 7; ++i) {
+    for (int i = 0; i < kSums; ++i) {
         A64[i] += (double)r.A[i];
         r.A[i] = 0.0f;
     }
@@ -294,9 +299,9 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
     r.lx = VFORM ? 0.0f : jscale;
     r.lv = r.le = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 7; ++i)
+    for (int i = 0; i < kSums; ++i)
         r.A[i] = 0.0f;
-    double A64[7] = {0, 0, 0, 0, 0, 0, 0};
+    double A64[kSums] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float *sub = a.sub;
     const int64_t N = a.N;
 
@@ -397,26 +402,28 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             }
         }
     }
-    // dJ/d(U0, a, D, d2, q, c) from the sums (FP64)
+    // dJ/d(U0, a, D, d2, q, c, gamma0, F0) from the sums (FP64)
     const double two_pi = 2.0 * 3.14159265358979323846;
-    double g[6];
+    double g[kGrad];
     g[0] = -two_pi * (A64[0] + (double)rc.a2 * A64[1]);
     g[1] = -(double)rc.four_pi_U0 * A64[1];
     g[2] = (double)rc.inv2D * A64[2];
     g[3] = A64[3] - A64[4];
     g[4] = A64[5];
     g[5] = -A64[6];
+    g[6] = -A64[7];
+    g[7] = A64[8];
     if (a.grad_particles && L.live) {
-        double *gp = a.grad_particles + 6 * ((int64_t)L.set * a.n + L.i);
+        double *gp = a.grad_particles + kGrad * ((int64_t)L.set * a.n + L.i);
 #pragma unroll
-        for (int i = 0; i < 6; ++i)
+        for (int i = 0; i < kGrad; ++i)
             gp[i] = g[i];
     }
-    // tile partials of the six gradient components (lanes past the end hold zeros)
+    // tile partials of the gradient components (lanes past the end hold zeros)
     if (L.tile * 64 < a.n) {
-        double *gp = a.grad_part + 6 * ((int64_t)L.set * a.tiles + L.tile);
+        double *gp = a.grad_part + kGrad * ((int64_t)L.set * a.tiles + L.tile);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < kGrad; ++i) {
             const double t = wave_sum(L.live ? g[i] : 0.0);
             if (L.lane == 0)
                 gp[i] = t;
@@ -436,16 +443,16 @@ __global__ __launch_bounds__(64) void k_adj_finalize(AdjArgs a, int32_t phase)
             a.loss[k] = o[0];
         return;
     }
-    const double *gp = a.grad_part + 6 * (int64_t)k * a.tiles;
+    const double *gp = a.grad_part + kGrad * (int64_t)k * a.tiles;
     const double scale = a.gloss[k] / (double)a.n;
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
+    for (int r = 0; r < kGrad; ++r) {
         double acc = 0.0;
         for (int64_t t = lane; t < a.tiles; t += 64)
-            acc += gp[6 * t + r];
+            acc += gp[kGrad * t + r];
         acc = wave_sum(acc);
         if (lane == 0)
-            a.grad[6 * (int64_t)k + r] = acc * scale;
+            a.grad[kGrad * (int64_t)k + r] = acc * scale;
     }
 }
 

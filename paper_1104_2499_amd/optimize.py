@@ -25,7 +25,7 @@ BOUNDS = {"U0": (0.05, 4.0), "a": (0.0, 0.5), "d2": (0.0, 2.0)}
 
 @dataclass
 class AdamResult:
-    theta: np.ndarray          # [n_sets, 6] final (U0, a, D, d2, q, c)
+    theta: np.ndarray          # [n_sets, 8] final (U0, a, D, d2, q, c, gamma0, F0)
     history: np.ndarray        # [iters + 1] mean |L| over sets before each step and at the end
     final_loss: np.ndarray     # [n_sets] adjoint forward loss at the final parameters
     verify_mean_v: np.ndarray  # [n_sets] plain batched integrator at the final parameters

@@ -16,15 +16,19 @@ import torch
 
 pytestmark = pytest.mark.gpu
 
-GRAD_KEYS = ("U0", "a", "D", "d2", "q", "c")
+GRAD_KEYS = ("U0", "a", "D", "d2", "q", "c", "gamma0", "F0")
 
 
 def _theta(n_sets, jitter=0.0, seed=0):
+    """Base parameters, each scaled by 1 + jitter * U(-1, 1); F0 (0 at the base) is shifted by
+    0.2 jitter U(-1, 1) instead."""
     from paper_1104_2499_amd.workloads import BASE_PARAMS
 
     base = np.array([BASE_PARAMS[k] for k in GRAD_KEYS])
     rng = np.random.default_rng(seed)
-    th = np.tile(base, (n_sets, 1)) * (1 + jitter * rng.uniform(-1, 1, (n_sets, 6)))
+    u = rng.uniform(-1, 1, (n_sets, len(GRAD_KEYS)))
+    th = np.tile(base, (n_sets, 1)) * (1 + jitter * u)
+    th[:, GRAD_KEYS.index("F0")] += 0.2 * jitter * u[:, GRAD_KEYS.index("F0")]
     return torch.tensor(th, dtype=torch.float64)
 
 
@@ -75,7 +79,9 @@ def test_gradient_matches_fp64_adjoint_short_horizon(gpu, orc):
     J, g = orc.adjoint(_params(theta[0]), x0, v0, e0, S, W, seed=42)
     g_ora = g.mean(axis=0)
     print("gpu", g_gpu, "\noracle", g_ora)
-    np.testing.assert_allclose(g_gpu, g_ora, rtol=1e-3)
+    # dL/dF0 nearly cancels over the ensemble (trapped particles: the equilibrium shift at both
+    # window ends); FP32 sums resolve it to about 1e-6 of the largest component, hence the atol
+    np.testing.assert_allclose(g_gpu, g_ora, rtol=1e-3, atol=1e-6 * np.abs(g_ora).max())
     assert abs(float(L.detach().cpu()[0]) - J.mean()) <= 1e-5
 
 
@@ -188,5 +194,5 @@ def test_decayed_estimator_matches_oracle(gpu, orc):
     for k in range(n_sets):
         x0, v0, e0 = orc.init_state(n, 8, k)
         _, go = orc.adjoint(_params(theta[k]), x0, v0, e0, S, W, seed=8, set_id=k, lookback=500)
-        np.testing.assert_allclose(g[k], go.mean(axis=0), rtol=1e-3,
-                                   atol=1e-6 * np.abs(go.mean(axis=0)).max())
+        want = go.mean(axis=0)
+        np.testing.assert_allclose(g[k], want, rtol=1e-3, atol=1e-6 * np.abs(want).max())

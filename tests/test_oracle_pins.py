@@ -292,38 +292,44 @@ def test_reduce_statistics_and_histogram_fixture(orc):
 # ----------------------------------------------------------------------------------------------
 # Adjoint
 # ----------------------------------------------------------------------------------------------
-def test_complex_step_real_part_is_the_forward(orc):
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_complex_step_real_part_is_the_forward(orc, scheme):
     x0, v0, e0 = orc.init_state(32, 42)
-    x, v, e, xs, _ = orc.integrate(None, x0, v0, e0, 800, win_begin=600)
+    x, v, e, xs, _ = orc.integrate(None, x0, v0, e0, 800, win_begin=600, scheme=scheme)
     J = (x - xs) / (200 * 1e-3)
-    for k in range(6):
-        _, Jre = orc.complex_step(None, k, x0, v0, e0, 800, 200)
+    for k in range(8):
+        _, Jre = orc.complex_step(None, k, x0, v0, e0, 800, 200, scheme=scheme)
         np.testing.assert_allclose(Jre, J, rtol=1e-12, atol=1e-12)
 
 
-def test_adjoint_matches_complex_step(orc):
-    """Reverse mode (adjoint) and forward mode (complex step) on the same FP64 path."""
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_adjoint_matches_complex_step(orc, scheme):
+    """Reverse mode (adjoint) and forward mode (complex step) on the same FP64 path, for all
+    eight parameters and both schemes."""
     n, S, W = 64, 1000, 200
     x0, v0, e0 = orc.init_state(n, 42)
-    J, g = orc.adjoint(None, x0, v0, e0, S, W)
-    for k in range(6):
-        cs, Jre = orc.complex_step(None, k, x0, v0, e0, S, W)
+    p = dict(F0=0.1, phi=0.07)
+    J, g = orc.adjoint(p, x0, v0, e0, S, W, scheme=scheme)
+    assert g.shape == (n, 8)
+    for k in range(8):
+        cs, Jre = orc.complex_step(p, k, x0, v0, e0, S, W, scheme=scheme)
         np.testing.assert_allclose(Jre, J, rtol=1e-12, atol=1e-12)
         scale = np.abs(cs).max()
         np.testing.assert_allclose(g[:, k], cs, rtol=1e-8, atol=1e-10 * scale)
 
 
-def test_adjoint_matches_central_differences(orc):
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_adjoint_matches_central_differences(orc, scheme):
     """Ensemble gradient vs central differences with common random numbers (h = 1e-4)."""
     n, S, W = 256, 1000, 200
     x0, v0, e0 = orc.init_state(n, 42)
-    _, g = orc.adjoint(None, x0, v0, e0, S, W)
+    _, g = orc.adjoint(None, x0, v0, e0, S, W, scheme=scheme)
     base = dict(orc.DEFAULTS)
     for k, name in enumerate(orc.GRAD_KEYS):
         def L(val):
             p = dict(base)
             p[name] = val
-            x, _, _, xs, _ = orc.integrate(p, x0, v0, e0, S, win_begin=S - W)
+            x, _, _, xs, _ = orc.integrate(p, x0, v0, e0, S, win_begin=S - W, scheme=scheme)
             return ((x - xs) / (W * 1e-3)).mean()
         h = 1e-4
         fd = (L(base[name] + h) - L(base[name] - h)) / (2 * h)
