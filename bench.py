@@ -152,9 +152,10 @@ def sweep_bench(reps: int = 2) -> dict:
             "finite_sets": int(np.isfinite(r.mean_v).sum())}
 
 
-def adjoint_bench(reps: int = 3) -> dict:
+def adjoint_bench(reps: int = 10, scheme: str = "em") -> dict:
     """Cost of the checkpointed adjoint (forward with checkpoints + backward) relative to the
-    plain forward of the same ensemble: 65536 particles, 1e4 EM steps, W = 2000, K = 100."""
+    plain forward of the same ensemble and scheme: 65536 particles, 1e4 steps, W = 2000,
+    K = 100."""
     import torch
 
     from paper_1104_2499_amd import adjoint, api
@@ -163,7 +164,7 @@ def adjoint_bench(reps: int = 3) -> dict:
     wl = WORKLOADS["adjoint-64k"]
     n, S, W, K = wl["n"], wl["steps"], wl["window"], wl["ckpt"]
     stream = torch.cuda.current_stream()
-    cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=K, seed=wl["seed"])
+    cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=K, seed=wl["seed"], scheme=scheme)
     theta = torch.tensor([[BASE_PARAMS[k] for k in adjoint.GRAD_KEYS]], dtype=torch.float64)
     rows = adjoint.param_rows(theta, cfg)
     ws = adjoint.workspace(1, cfg)
@@ -173,7 +174,8 @@ def adjoint_bench(reps: int = 3) -> dict:
 
     def plain():
         api.reset_state(state, wl["seed"])
-        api.integrate(state, S, BASE_PARAMS, wl["dt"], "em", wl["seed"], 0, 0, S - W, snap, rws, 0)
+        api.integrate(state, S, BASE_PARAMS, wl["dt"], scheme, wl["seed"], 0, 0, S - W, snap, rws,
+                      0)
         return api.reduce(rws, n, 0, W * wl["dt"])[0]
 
     def timed(fn):
@@ -192,7 +194,8 @@ def adjoint_bench(reps: int = 3) -> dict:
     t_bwd = timed(lambda: adjoint.backward(rows, cfg, ws, gloss))
     loss = float(adjoint.forward(rows, cfg, ws)[0].cpu())
     mean_v = float(plain()[0].cpu())
-    return {"workload": "adjoint-64k", "plain_forward_ms": t_plain, "adjoint_forward_ms": t_fwd,
+    return {"workload": "adjoint-64k", "scheme": scheme, "plain_forward_ms": t_plain,
+            "adjoint_forward_ms": t_fwd,
             "adjoint_backward_ms": t_bwd, "cost_ratio": (t_fwd + t_bwd) / t_plain,
             "loss_equals_forward_mean": loss == mean_v,
             "particle_steps": n * S}
@@ -324,6 +327,7 @@ def main() -> int:
     if not args.no_sweep:
         line["sweep"] = sweep_bench()
         line["adjoint"] = adjoint_bench()
+        line["adjoint_heun"] = adjoint_bench(scheme="heun")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, BASE_PARAMS)
     print(json.dumps(line), flush=True)

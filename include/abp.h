@@ -169,20 +169,23 @@ abp_status abp_integrate_batched(int32_t n_sets, const abp_params *h_params,
                                  double *d_out, uint64_t *d_hist, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
- * Pathwise gradient of the window mean velocity (Euler-Maruyama), by a discrete adjoint with
- * checkpoints every ckpt_every steps and Philox noise regenerated in the backward pass.
+ * Pathwise gradient of the window mean velocity (Euler-Maruyama or stochastic Heun), by a discrete
+ * adjoint with checkpoints every ckpt_every steps and Philox noise regenerated in the backward pass.
  * ------------------------------------------------------------------------------------------- */
 typedef struct abp_adjoint_cfg {
     double dt;           /* > 0 */
     int64_t n_steps;     /* S >= 1 */
     int64_t window;      /* W, 1 <= W <= S: the loss averages over the last W steps */
     int64_t ckpt_every;  /* K >= 1: forward checkpoint interval (e.g. about sqrt(S)); rounded up
-                            to a multiple of 16, the backward pass's register-staging window. The
-                            gradient does not depend on K (bit for bit) */
+                            to a multiple of 16 (the backward pass stages 16 Euler-Maruyama or 8
+                            Heun steps at a time in registers). The gradient does not depend on K
+                            (bit for bit) */
     uint64_t seed;       /* Philox key; set k uses counter word 2 = k */
-    int64_t lookback;    /* 0: exact pathwise gradient. T > 0: each window velocity's sensitivity
-                            is damped by (1 - 1/T) per step of look-back (a biased, bounded-variance
-                            estimator for long chaotic horizons) */
+    int64_t lookback;    /* 0: exact pathwise gradient. T > 0 (Euler-Maruyama only): each window
+                            velocity's sensitivity is damped by (1 - 1/T) per step of look-back (a
+                            biased, bounded-variance estimator for long chaotic horizons) */
+    int32_t scheme;      /* ABP_EM or ABP_HEUN: the map whose discrete adjoint is taken */
+    int32_t pad;
 } abp_adjoint_cfg;
 
 /* Bytes of workspace: checkpoints (28 bytes per particle per segment), sub-checkpoints, and the
@@ -191,13 +194,13 @@ size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set, int64_t n_
                                    int64_t ckpt_every);
 
 /* phase 0 (forward): for each set k (parameters h_params[k], D > 0; n_per_set particles with ids
- * 0..n-1 from the workload initial condition) integrate S steps of Euler-Maruyama, store the
+ * 0..n-1 from the workload initial condition) integrate S steps of cfg->scheme, store the
  * checkpoints in d_ws, and write d_loss[k] = L_k = (1/n) sum_i (x_S - x_{S-W}) / (W dt), the same
  * value abp_integrate + abp_reduce give for that set alone with set_id = k.
  * phase 1 (backward): with d_ws left by phase 0 for identical arguments, write
  * d_grad[8k + j] = d_gloss[k] * dL_k/dtheta_j, theta = (U0, a, D, d2, q, c, gamma0, F0), and,
- * if d_grad_particles is non-NULL, d_grad_particles[8 (k n + i) + j] = dJ_i/dtheta_j of particle i of
- * set k (unscaled; used for per-particle checks and gradient statistics).
+ * if d_grad_particles is non-NULL, d_grad_particles[8 (k n + i) + j] = dJ_i/dtheta_j of particle
+ * i of set k (unscaled; used for per-particle checks and gradient statistics).
  * h_params is read during the call (its per-set constants are staged into d_ws, after which the
  * call waits for the stream to drain); the kernels then run asynchronously on `stream`. */
 abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_params *h_params,

@@ -3,7 +3,8 @@
 theta [n_sets, 8] float64 holds (U0, a, D, d2, q, c, gamma0, F0) per parameter set; the phase phi
 of the potential, Eq. (4), is fixed by the config. The forward pass runs abp_adjoint phase 0
 (integrate with checkpoints, loss L_k = mean velocity of set k over the last W steps); backward
-runs phase 1 (checkpointed discrete adjoint with regenerated noise). All arithmetic is in the HIP
+runs phase 1 (checkpointed discrete adjoint of the Euler-Maruyama or Heun map, with regenerated
+noise). All arithmetic is in the HIP
 library; torch provides the buffers and the stream.
 """
 from __future__ import annotations
@@ -15,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from .api import _stream, check
+from .api import SCHEMES, _stream, check
 from .workloads import BASE_PARAMS, PARAM_KEYS
 
 GRAD_KEYS = ("U0", "a", "D", "d2", "q", "c", "gamma0", "F0")
@@ -30,11 +31,14 @@ class AdjointConfig:
     dt: float = 1e-3
     seed: int = 42
     lookback: int = 0         # 0 = exact gradient; T > 0 = sensitivities damped by (1 - 1/T)/step
+    scheme: str = "em"        # "em" or "heun" (lookback > 0 needs "em")
     fixed: dict = field(default_factory=lambda: {"phi": BASE_PARAMS["phi"]})
 
     def abi(self) -> _lib.AbpAdjointCfg:
+        if self.scheme not in SCHEMES:
+            raise ValueError(f"scheme must be one of {sorted(SCHEMES)}")
         return _lib.AbpAdjointCfg(self.dt, self.steps, self.window, self.ckpt, self.seed,
-                                  self.lookback)
+                                  self.lookback, SCHEMES[self.scheme], 0)
 
 
 def param_rows(theta: torch.Tensor, cfg: AdjointConfig) -> np.ndarray:

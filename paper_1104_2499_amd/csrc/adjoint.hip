@@ -1,5 +1,6 @@
-// adjoint.hip -- pathwise gradients of the window mean velocity through the Euler-Maruyama map
-// (Eqs. (1)-(3)), by a discrete adjoint with checkpointing and noise regeneration.
+// adjoint.hip -- pathwise gradients of the window mean velocity through the Euler-Maruyama or
+// stochastic Heun map (Eqs. (1)-(3)), by a discrete adjoint with checkpointing and noise
+// regeneration.
 //
 // Loss of set k: L_k = (1/N) sum_i J_i, J_i = (x_S - x_{S-W}) / (W dt), i.e. the mean drift
 // velocity that abp_integrate reports for the same set (bit for bit). Gradient order:
@@ -8,18 +9,18 @@
 // Forward phase: each lane integrates its particle from the workload initial condition and stores
 // its whole state (28 bytes) every K steps. Backward phase: for each segment [jK, (j+1)K) in
 // reverse, the lane restores the checkpoint and recomputes the segment with regenerated Philox
-// noise, leaving sub-checkpoints at absolute multiples of B = 16 steps in workspace memory (K is
-// rounded up to a multiple of B); then, for each sub-window in reverse, it restores the
-// sub-checkpoint, recomputes the sub-window while
-// staging the values the reverse step needs (cos and sin of the phase, v, e, sigma*xi) in
-// registers, and runs the adjoint recursion backwards over it. The recomputation reproduces the
+// noise, leaving sub-checkpoints at absolute multiples of B steps in workspace memory (B = 16 for
+// Euler-Maruyama, 8 for Heun; K is rounded up to a multiple of 16); then, for each sub-window in
+// reverse, it restores the sub-checkpoint, recomputes the sub-window while staging the values the
+// reverse step needs (cos and sin of the phase, v, e at every point where the drift is evaluated,
+// and sigma*xi) in registers, and runs the adjoint recursion backwards over it. The recomputation reproduces the
 // forward bits exactly (the integrator's state is resumable mid-block), so the result does not
 // depend on K. Per-step gradient terms are summed in FP32 within each absolute B-step window and
 // in FP64 across windows (that grouping does not depend on K either); tiles of 64 particles and
 // sets are then reduced in a fixed order.
 //
 // Workspace layout (abp_adjoint_workspace_bytes):
-//   AdjRow rows[n_sets] | float ckpt[n_seg][7][N] | float sub[n_sub][7][N] |
+//   AdjRow rows[n_sets] | float ckpt[n_seg][7][N] | float sub[K/8][7][N] |
 //   double loss_part[n_sets][tiles][2] | double grad_part[n_sets][tiles][8]
 // (N = n_sets * tiles * 64 checkpoint slots: one per lane, also past a set's last particle)
 #include <vector>
@@ -47,7 +48,7 @@ struct AdjRow {
 struct AdjArgs {
     const AdjRow *rows;
     float *ckpt;        // [n_seg][7][N]
-    float *sub;         // [n_sub][7][N]
+    float *sub;         // [K/8][7][N]
     double *loss_part;  // [n_sets][tiles][2]
     double *grad_part;  // [n_sets][tiles][8]
     const double *gloss;
@@ -58,7 +59,6 @@ struct AdjArgs {
     int64_t N;          // checkpoint slots (64 per tile)
     int64_t tiles;      // tiles per set
     int64_t S, W, K;    // steps, window, checkpoint interval
-    int64_t n_sub;      // sub-checkpoint slots per segment
     double dt;
     uint32_t k0, k1;
     int32_t n_sets;
@@ -66,8 +66,9 @@ struct AdjArgs {
     int32_t vform;    // 1: the loss enters as (1/W) sum of v_n over the window (used with rho < 1)
 };
 
-constexpr int kStage = 16;  // B: steps staged in registers per sub-window (multiple of 4)
-constexpr int kGrad = 8;    // gradient components: U0, a, D, d2, q, c, gamma0, F0
+constexpr int kAlign = 16;    // checkpoint intervals are multiples of this
+constexpr int kMinStage = 8;  // the shortest staging window (sub-checkpoint slots: K / 8)
+constexpr int kGrad = 8;      // gradient components: U0, a, D, d2, q, c, gamma0, F0
 
 struct AdjLayout {
     size_t rows, ckpt, sub, loss, grad, total;
@@ -76,16 +77,16 @@ struct AdjLayout {
 
 // Every lane of every wave (also lanes past a set's last particle) owns one slot in the
 // checkpoint planes: N = n_sets * tiles * 64.
-// Checkpoint interval actually used: the requested K rounded up to a multiple of the staging
-// window, so that every segment starts on a sub-window boundary.
-inline int64_t effective_K(int64_t K) { return (K + kStage - 1) / kStage * kStage; }
+// Checkpoint interval actually used: the requested K rounded up to a multiple of 16, so that every
+// segment starts on a sub-window boundary of either scheme.
+inline int64_t effective_K(int64_t K) { return (K + kAlign - 1) / kAlign * kAlign; }
 
 inline AdjLayout adj_layout(int32_t n_sets, int64_t n, int64_t S, int64_t K)
 {
     AdjLayout L;
     K = effective_K(K);
     L.n_seg = (S + K - 1) / K;
-    L.n_sub = K / kStage;
+    L.n_sub = K / kMinStage;
     L.tiles = (n + 63) / 64;
     const size_t N = (size_t)n_sets * (size_t)L.tiles * 64;
     L.rows = 0;
@@ -157,6 +158,7 @@ __device__ __forceinline__ Particle initial_particle(uint32_t pid, uint32_t set,
 }
 
 // Forward phase: integrate, store a checkpoint at every multiple of K, reduce the loss.
+template <int SCHEME>
 __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
 {
     Lane L;
@@ -173,10 +175,10 @@ __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
         put_state(a.ckpt + (size_t)j * 7 * a.N, a.N, L.g, p[0]);
         const int64_t end = (j + 1) * a.K < a.S ? (j + 1) * a.K : a.S;
         if (wb >= step && wb < end) {
-            advance<0, 1, 1>(row.k, s, pid, p, step, wb);
+            advance<SCHEME, 1, 1>(row.k, s, pid, p, step, wb);
             xs[0] = position64(p[0].cell, p[0].xf, p[0].lx);
         }
-        advance<0, 1, 1>(row.k, s, pid, p, step, end);
+        advance<SCHEME, 1, 1>(row.k, s, pid, p, step, end);
     }
     if (wb == a.S)
         xs[0] = position64(p[0].cell, p[0].xf, p[0].lx);
@@ -186,25 +188,52 @@ __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
                     nullptr);
 }
 
-// Values of one sub-window staged for the reverse sweep: cos and sin of the phase 2 pi (x + phi),
-// v, e (the rounded sums the drift saw) and sigma xi, per step.
-struct Stage {
-    float c[kStage], s[kStage], v[kStage], e[kStage], z[kStage];
+// Values of one sub-window staged for the reverse sweep, per step: cos and sin of the phase
+// 2 pi (x + phi), v and e (the rounded sums the drift saw), sigma xi; for Heun also the same at
+// the predictor point.
+template <int SCHEME>
+struct Stage;
+
+template <>
+struct Stage<0> {
+    static constexpr int B = 16;
+    float c[B], s[B], v[B], e[B], z[B];
 };
 
-// Recompute slot t of a sub-window (absolute step base + t), staging its inputs.
+template <>
+struct Stage<1> {
+    static constexpr int B = 8;
+    float c[B], s[B], v[B], e[B], ct[B], st[B], vt[B], et[B], z[B];
+};
+
+// Recompute slot t of a sub-window (absolute step base + t), staging its inputs. The staged
+// predictor repeats step_heun's own expressions, so it holds the values that step saw.
+template <int SCHEME>
 __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_t pid, Particle &q,
-                                         float &xb, Noise4 &z, int64_t base, int t, Stage &B)
+                                         float &xb, Noise4 &z, int64_t base, int t,
+                                         Stage<SCHEME> &B)
 {
     if ((t & 3) == 0)
         z = noise_block((uint32_t)((base + t) >> 2), pid, s.set, s.k0, s.k1, k.bm);
+    const float zs = z.z[t & 3];
     const float xc = xb + q.lx, vc = q.v + q.lv, ec = q.e + q.le;
     B.c[t] = __builtin_amdgcn_cosf(xc);
     B.s[t] = __builtin_amdgcn_sinf(xc);
     B.v[t] = vc;
     B.e[t] = ec;
-    B.z[t] = z.z[t & 3];
-    step_em(k, q, xb, z.z[t & 3]);
+    B.z[t] = zs;
+    if constexpr (SCHEME == 1) {
+        float fv0, fe0;
+        drift(k, xc, vc, ec, fv0, fe0);
+        const float xp = fmaf(vc, k.dt, xc);
+        const float vp = vc + fmaf(fv0, k.dt, zs);
+        const float ep = fmaf(fe0, k.dt, ec);
+        B.ct[t] = __builtin_amdgcn_cosf(xp);
+        B.st[t] = __builtin_amdgcn_sinf(xp);
+        B.vt[t] = vp;
+        B.et[t] = ep;
+    }
+    step<SCHEME>(k, q, xb, zs);
     if ((t & 3) == 3) {
         end_block(q);
         xb = q.xf + k.phi;
@@ -224,7 +253,8 @@ struct Rev {
 };
 
 template <int VFORM>
-__device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const Stage &B, int t,
+__device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc, const Stage<0> &B,
+                                            int t,
                                          int64_t n, int64_t wb, float jscale, float invW, float rho,
                                          Rev &r)
 {
@@ -261,6 +291,65 @@ __device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const
     }
 }
 
+// Reverse of one stochastic Heun step y' = y + dt/2 (f(y) + f(yp)) + sigma xi e_v with predictor
+// yp = y + dt f(y) + sigma xi e_v, lam' = lam_{n+1}:
+//   mu = J(yp)^T lam',  nu = lam' + dt mu,  lam_n = lam' + dt/2 (mu + J(y)^T nu);
+// the parameter terms are dt/2 f_theta(yp)^T lam' + dt/2 f_theta(y)^T nu, and sigma enters
+// through both the corrector and the predictor: (lam'_v + dt/2 mu_v) xi.
+__device__ __forceinline__ void jac_t(const Coef &k, const RevCoef &rc, float c, float sn, float v,
+                                      float e, float wx, float wv, float we, float &ox, float &ov,
+                                      float &oe)
+{
+    const float upp = rc.m4pi2U0 * (sn * fmaf(rc.eight_a, c, 1.0f));  // U''(x)
+    const float d2v = k.d2 * v;
+    ox = -upp * wv;
+    ov = fmaf(-2.0f * d2v * e, we, fmaf(fmaf(k.d2, e, -k.g0), wv, wx));
+    oe = fmaf(d2v, wv, -fmaf(d2v, v, k.c) * we);
+}
+
+__device__ __forceinline__ void add_terms(Rev &r, float c, float v, float e, float wv, float we)
+{
+    const float ev = e * v;
+    r.A[0] = fmaf(wv, c, r.A[0]);
+    r.A[1] = fmaf(wv, fmaf(c + c, c, -1.0f), r.A[1]);
+    r.A[3] = fmaf(wv, ev, r.A[3]);
+    r.A[4] = fmaf(we * ev, v, r.A[4]);
+    r.A[5] += we;
+    r.A[6] = fmaf(we, e, r.A[6]);
+    r.A[7] = fmaf(wv, v, r.A[7]);
+    r.A[8] += wv;
+}
+
+__device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc, const Stage<1> &B,
+                                              int t, int64_t n, int64_t wb, float jscale, Rev &r)
+{
+    if (n + 1 == wb)
+        r.lx -= jscale;
+    const float h = k.half_dt;
+    float mx, mv, me;
+    jac_t(k, rc, B.ct[t], B.st[t], B.vt[t], B.et[t], r.lx, r.lv, r.le, mx, mv, me);
+    const float nx = fmaf(k.dt, mx, r.lx), nv = fmaf(k.dt, mv, r.lv), ne = fmaf(k.dt, me, r.le);
+    float px, pv, pe;
+    jac_t(k, rc, B.c[t], B.s[t], B.v[t], B.e[t], nx, nv, ne, px, pv, pe);
+    add_terms(r, B.ct[t], B.vt[t], B.et[t], h * r.lv, h * r.le);
+    add_terms(r, B.c[t], B.v[t], B.e[t], h * nv, h * ne);
+    r.A[2] = fmaf(fmaf(h, mv, r.lv), B.z[t], r.A[2]);
+    r.lx = fmaf(h, mx + px, r.lx);
+    r.lv = fmaf(h, mv + pv, r.lv);
+    r.le = fmaf(h, me + pe, r.le);
+}
+
+template <int SCHEME, int VFORM>
+__device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const Stage<SCHEME> &B,
+                                         int t, int64_t n, int64_t wb, float jscale, float invW,
+                                         float rho, Rev &r)
+{
+    if constexpr (SCHEME == 0)
+        rev_slot_em<VFORM>(k, rc, B, t, n, wb, jscale, invW, rho, r);
+    else
+        rev_slot_heun(k, rc, B, t, n, wb, jscale, r);
+}
+
 __device__ __forceinline__ void flush(Rev &r, double (&A64)[kSums])
 {
 #pragma unroll
@@ -271,15 +360,16 @@ __device__ __forceinline__ void flush(Rev &r, double (&A64)[kSums])
 }
 
 // Backward phase. lam = dJ_i/dy_{n+1} while step n is reversed. VFORM selects the decayed
-// estimator (see abp_adjoint_cfg.lookback).
+// estimator (see abp_adjoint_cfg.lookback; Euler-Maruyama only).
 //
 // Within a segment the sub-windows are processed as a software pipeline: while window m is
 // reversed from one staging buffer, window m-1 is recomputed into the other, in the same
 // instruction stream, so the two dependency chains fill each other's latency (the adjoint runs
 // at one wavefront per SIMD for 2^16-particle ensembles).
-template <int VFORM>
+template <int SCHEME, int VFORM>
 __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
 {
+    constexpr int kStage = Stage<SCHEME>::B;
     Lane L;
     if (!locate(a, L))
         return;
@@ -319,12 +409,12 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
         int64_t step = s0;
         for (int64_t m = m0; m < m1; ++m) {
             put_state(sub + (size_t)(m - m0) * 7 * N, N, L.g, p[0]);
-            advance<0, 1, 1>(k, s, pid, p, step, (m + 1) * kStage);
+            advance<SCHEME, 1, 1>(k, s, pid, p, step, (m + 1) * kStage);
         }
         if (j > 0)
             ck = get_state(a.ckpt + (size_t)(j - 1) * 7 * N, N, L.g);
 
-        Stage SA, SB;
+        Stage<SCHEME> SA, SB;
         Noise4 z;
         Particle q = p[0];
         int64_t m = m1;
@@ -335,11 +425,12 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
 #pragma unroll
             for (int t = 0; t < kStage; ++t)
                 if (t < hi1)
-                    rec_slot(k, s, pid[0], q, xb, z, m1 * kStage, t, SA);
+                    rec_slot<SCHEME>(k, s, pid[0], q, xb, z, m1 * kStage, t, SA);
 #pragma unroll
             for (int t = kStage - 1; t >= 0; --t)
                 if (t < hi1)
-                    rev_slot<VFORM>(k, rc, SA, t, m1 * kStage + t, wb, jscale, invW, rho, r);
+                    rev_slot<SCHEME, VFORM>(k, rc, SA, t, m1 * kStage + t, wb, jscale, invW,
+                                            rho, r);
             flush(r, A64);
             if (m1 == m0)
                 continue;
@@ -351,7 +442,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             float xb = q.xf + k.phi;
 #pragma unroll
             for (int t = 0; t < kStage; ++t)
-                rec_slot(k, s, pid[0], q, xb, z, m * kStage, t, SA);
+                rec_slot<SCHEME>(k, s, pid[0], q, xb, z, m * kStage, t, SA);
         }
         Particle nxt;
         if (m > m0)
@@ -361,7 +452,8 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             if (m == m0) {
 #pragma unroll
                 for (int t = kStage - 1; t >= 0; --t)
-                    rev_slot<VFORM>(k, rc, SA, t, m * kStage + t, wb, jscale, invW, rho, r);
+                    rev_slot<SCHEME, VFORM>(k, rc, SA, t, m * kStage + t, wb, jscale, invW,
+                                            rho, r);
                 flush(r, A64);
                 break;
             }
@@ -372,9 +464,10 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
                 float xb = q.xf + k.phi;
 #pragma unroll
                 for (int t = 0; t < kStage; ++t) {
-                    rec_slot(k, s, pid[0], q, xb, z, (m - 1) * kStage, t, SB);
+                    rec_slot<SCHEME>(k, s, pid[0], q, xb, z, (m - 1) * kStage, t, SB);
                     const int u = kStage - 1 - t;
-                    rev_slot<VFORM>(k, rc, SA, u, m * kStage + u, wb, jscale, invW, rho, r);
+                    rev_slot<SCHEME, VFORM>(k, rc, SA, u, m * kStage + u, wb, jscale, invW,
+                                            rho, r);
                 }
                 flush(r, A64);
                 --m;
@@ -382,7 +475,8 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             if (m == m0) {
 #pragma unroll
                 for (int t = kStage - 1; t >= 0; --t)
-                    rev_slot<VFORM>(k, rc, SB, t, m * kStage + t, wb, jscale, invW, rho, r);
+                    rev_slot<SCHEME, VFORM>(k, rc, SB, t, m * kStage + t, wb, jscale, invW,
+                                            rho, r);
                 flush(r, A64);
                 break;
             }
@@ -393,9 +487,10 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
                 float xb = q.xf + k.phi;
 #pragma unroll
                 for (int t = 0; t < kStage; ++t) {
-                    rec_slot(k, s, pid[0], q, xb, z, (m - 1) * kStage, t, SA);
+                    rec_slot<SCHEME>(k, s, pid[0], q, xb, z, (m - 1) * kStage, t, SA);
                     const int u = kStage - 1 - t;
-                    rev_slot<VFORM>(k, rc, SB, u, m * kStage + u, wb, jscale, invW, rho, r);
+                    rev_slot<SCHEME, VFORM>(k, rc, SB, u, m * kStage + u, wb, jscale, invW,
+                                            rho, r);
                 }
                 flush(r, A64);
                 --m;
@@ -479,7 +574,9 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         return ABP_E_ARG;
     if (!(cfg->dt > 0.0) || !is_finite(cfg->dt) || cfg->n_steps < 1 ||
         cfg->n_steps > kMaxStepIndex || cfg->window < 1 || cfg->window > cfg->n_steps ||
-        cfg->ckpt_every < 1 || cfg->lookback < 0)
+        cfg->ckpt_every < 1 || cfg->lookback < 0 ||
+        (cfg->scheme != ABP_EM && cfg->scheme != ABP_HEUN) ||
+        (cfg->scheme == ABP_HEUN && cfg->lookback > 0))
         return ABP_E_ARG;
     for (int32_t k = 0; k < n_sets; ++k)
         if (!params_ok(h_params[k]) || !(h_params[k].D > 0.0))
@@ -534,7 +631,6 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
     a.S = cfg->n_steps;
     a.W = cfg->window;
     a.K = effective_K(cfg->ckpt_every);
-    a.n_sub = L.n_sub;
     const Stream ks = make_stream(cfg->seed, 0);
     a.k0 = ks.k0;
     a.k1 = ks.k1;
@@ -543,12 +639,17 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
     a.rho = cfg->lookback > 0 ? (float)(1.0 - 1.0 / (double)cfg->lookback) : 1.0f;
     const int64_t waves = (int64_t)n_sets * L.tiles;
     const unsigned grid = (unsigned)((waves * 64 + 255) / 256);
-    if (phase == 0)
-        hipLaunchKernelGGL(k_adj_forward, dim3(grid), dim3(256), 0, st, a);
+    const bool heun = cfg->scheme == ABP_HEUN;
+    if (phase == 0 && heun)
+        hipLaunchKernelGGL(k_adj_forward<1>, dim3(grid), dim3(256), 0, st, a);
+    else if (phase == 0)
+        hipLaunchKernelGGL(k_adj_forward<0>, dim3(grid), dim3(256), 0, st, a);
+    else if (heun)
+        hipLaunchKernelGGL((k_adj_backward<1, 0>), dim3(grid), dim3(256), 0, st, a);
     else if (a.vform)
-        hipLaunchKernelGGL(k_adj_backward<1>, dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_adj_backward<0, 1>), dim3(grid), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL(k_adj_backward<0>, dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_adj_backward<0, 0>), dim3(grid), dim3(256), 0, st, a);
     if (hipGetLastError() != hipSuccess)
         return ABP_E_HIP;
     hipLaunchKernelGGL(k_adj_finalize, dim3((unsigned)n_sets), dim3(64), 0, st, a, phase);

@@ -196,3 +196,56 @@ def test_decayed_estimator_matches_oracle(gpu, orc):
         _, go = orc.adjoint(_params(theta[k]), x0, v0, e0, S, W, seed=8, set_id=k, lookback=500)
         want = go.mean(axis=0)
         np.testing.assert_allclose(g[k], want, rtol=1e-3, atol=1e-6 * np.abs(want).max())
+
+
+def test_heun_loss_and_checkpoint_invariance(gpu):
+    """G4 for the stochastic Heun adjoint: loss == the Heun integrator's mean velocity and the
+    gradient does not depend on K (8-step staging, K rounded to 16)."""
+    from paper_1104_2499_amd import adjoint, api
+
+    theta = _theta(2, jitter=0.2, seed=6)
+    grads = []
+    for K in (100, 37, 1203):
+        cfg = adjoint.AdjointConfig(n=200, steps=1203, window=401, ckpt=K, seed=6, scheme="heun")
+        rows = adjoint.param_rows(theta, cfg)
+        ws = adjoint.workspace(2, cfg)
+        loss = adjoint.forward(rows, cfg, ws)
+        g, gp = adjoint.backward(rows, cfg, ws, torch.ones(2, dtype=torch.float64),
+                                 per_particle=True)
+        grads.append((g.cpu().numpy(), gp.cpu().numpy()))
+        for k in range(2):
+            r = api.run(_params(theta[k]), n=200, steps=1203, window=401, scheme="heun", seed=6,
+                        bins=0, set_id=k)
+            assert float(loss[k].cpu()) == r.mean_v
+    for g, gp in grads[1:]:
+        np.testing.assert_array_equal(g, grads[0][0])
+        np.testing.assert_array_equal(gp, grads[0][1])
+
+
+def test_heun_gradient_matches_fp64_adjoint(gpu, orc):
+    """G2 for Heun: 3 sets x 1024 particles, S = 1e3, W = 200, against the FP64 Heun adjoint."""
+    from paper_1104_2499_amd import adjoint
+
+    n_sets, n, S, W = 3, 1024, 1000, 200
+    theta = _theta(n_sets, jitter=0.2, seed=12)
+    cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=100, seed=12, scheme="heun")
+    t = theta.clone().requires_grad_(True)
+    L = adjoint.mean_velocity(t, cfg)
+    L.sum().backward()
+    for k in range(n_sets):
+        x0, v0, e0 = orc.init_state(n, 12, k)
+        J, g = orc.adjoint(_params(theta[k]), x0, v0, e0, S, W, seed=12, set_id=k,
+                           scheme=orc.HEUN)
+        want = g.mean(axis=0)
+        print("gpu", t.grad.numpy()[k], "\noracle", want)
+        np.testing.assert_allclose(t.grad.numpy()[k], want, rtol=1e-3,
+                                   atol=1e-6 * np.abs(want).max())
+        assert abs(float(L.detach().cpu()[k]) - J.mean()) <= 1e-5
+
+
+def test_heun_rejects_lookback(gpu):
+    from paper_1104_2499_amd import adjoint, api
+
+    cfg = adjoint.AdjointConfig(n=64, steps=100, window=10, ckpt=10, scheme="heun", lookback=50)
+    with pytest.raises(api.AbpError, match="ABP_E_ARG"):
+        adjoint.forward(adjoint.param_rows(_theta(1), cfg), cfg, adjoint.workspace(1, cfg))
