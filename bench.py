@@ -215,7 +215,14 @@ def main() -> int:
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device copy (reference for HBM counters)")
     ap.add_argument("--tune", default=None, help="block,ppl,unroll (default: library default)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint cost measurements (EM and Heun), one JSON line each")
     args = ap.parse_args()
+
+    if args.adjoint_only:
+        for scheme in ("em", "heun"):
+            print(json.dumps(adjoint_bench(scheme=scheme)), flush=True)
+        return 0
 
     if args.copy_probe:
         # a plain device-to-device copy of known size: the reference that scales the HBM
@@ -232,8 +239,8 @@ def main() -> int:
         return 0
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
-              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the ensemble would "
+              "shard by particles or parameter sets); run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
