@@ -252,14 +252,22 @@ struct Rev {
     float A[kSums];
 };
 
-template <int VFORM>
+// Loss-side constants of the reverse sweep. wb = S - W. The exact form injects -1/(W dt) into
+// lam_x at state index wb; the decayed form adds 1/W to lam_v at every window step n >= wb. Only
+// the one sub-window holding step wb - 1 tests n per slot (CHECK); every other sub-window is
+// entirely before or after the window start and takes the wavefront-uniform add_w instead.
+struct RevCtx {
+    int64_t wb;
+    float jscale, invW, rho;
+};
+
+template <int VFORM, bool CHECK>
 __device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc, const Stage<0> &B,
-                                            int t,
-                                         int64_t n, int64_t wb, float jscale, float invW, float rho,
-                                         Rev &r)
+                                            int t, int64_t n, const RevCtx &cx, float add_w,
+                                            Rev &r)
 {
-    if (!VFORM && n + 1 == wb)
-        r.lx -= jscale;  // the window-start position enters J with weight -1/(W dt)
+    if (CHECK && !VFORM && n + 1 == cx.wb)
+        r.lx -= cx.jscale;  // the window-start position enters J with weight -1/(W dt)
     const float c = B.c[t], sn = B.s[t], v = B.v[t], e = B.e[t];
     const float lvdt = r.lv * k.dt, ledt = r.le * k.dt;
     const float c2 = fmaf(c + c, c, -1.0f);  // cos 2th
@@ -281,9 +289,9 @@ __device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc, co
     const float d2v = k.d2 * v;
     const float nle = fmaf(lvdt, d2v, fmaf(-ledt, fmaf(d2v, v, k.c), r.le));
     if (VFORM) {
-        r.lx = rho * nlx;
-        r.lv = fmaf(rho, nlv, n >= wb ? invW : 0.0f);
-        r.le = rho * nle;
+        r.lx = cx.rho * nlx;
+        r.lv = fmaf(cx.rho, nlv, CHECK ? (n >= cx.wb ? cx.invW : 0.0f) : add_w);
+        r.le = cx.rho * nle;
     } else {
         r.lx = nlx;
         r.lv = nlv;
@@ -320,11 +328,12 @@ __device__ __forceinline__ void add_terms(Rev &r, float c, float v, float e, flo
     r.A[8] += wv;
 }
 
+template <bool CHECK>
 __device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc, const Stage<1> &B,
-                                              int t, int64_t n, int64_t wb, float jscale, Rev &r)
+                                              int t, int64_t n, const RevCtx &cx, Rev &r)
 {
-    if (n + 1 == wb)
-        r.lx -= jscale;
+    if (CHECK && n + 1 == cx.wb)
+        r.lx -= cx.jscale;
     const float h = k.half_dt;
     float mx, mv, me;
     jac_t(k, rc, B.ct[t], B.st[t], B.vt[t], B.et[t], r.lx, r.lv, r.le, mx, mv, me);
@@ -339,15 +348,80 @@ __device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc, 
     r.le = fmaf(h, me + pe, r.le);
 }
 
-template <int SCHEME, int VFORM>
+template <int SCHEME, int VFORM, bool CHECK>
 __device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const Stage<SCHEME> &B,
-                                         int t, int64_t n, int64_t wb, float jscale, float invW,
-                                         float rho, Rev &r)
+                                         int t, int64_t n, const RevCtx &cx, float add_w, Rev &r)
 {
     if constexpr (SCHEME == 0)
-        rev_slot_em<VFORM>(k, rc, B, t, n, wb, jscale, invW, rho, r);
+        rev_slot_em<VFORM, CHECK>(k, rc, B, t, n, cx, add_w, r);
     else
-        rev_slot_heun(k, rc, B, t, n, wb, jscale, r);
+        rev_slot_heun<CHECK>(k, rc, B, t, n, cx, r);
+}
+
+// Reverse the first `hi` slots of a staged sub-window starting at absolute step base, last first.
+template <int SCHEME, int VFORM, bool CHECK>
+__device__ __forceinline__ void rev_window(const Coef &k, const RevCoef &rc,
+                                           const Stage<SCHEME> &B, int64_t base, int hi,
+                                           const RevCtx &cx, float add_w, Rev &r)
+{
+#pragma unroll
+    for (int t = Stage<SCHEME>::B - 1; t >= 0; --t)
+        if (t < hi)
+            rev_slot<SCHEME, VFORM, CHECK>(k, rc, B, t, base + t, cx, add_w, r);
+}
+
+// Recompute the first `hi` slots of the sub-window starting at absolute step base from q,
+// staging them into B.
+template <int SCHEME>
+__device__ __forceinline__ void rec_window(const Coef &k, const Stream &s, uint32_t pid,
+                                           Particle &q, int64_t base, int hi, Stage<SCHEME> &B)
+{
+    Noise4 z;
+    float xb = q.xf + k.phi;
+#pragma unroll
+    for (int t = 0; t < Stage<SCHEME>::B; ++t)
+        if (t < hi)
+            rec_slot<SCHEME>(k, s, pid, q, xb, z, base, t, B);
+}
+
+// One pipeline trip: reverse window m from R while recomputing window m-1 (from q) into W. The
+// sub-window holding the loss-window start (m == m_chk) runs the two halves one after the other.
+template <int SCHEME, int VFORM>
+__device__ __forceinline__ void trip(const Coef &k, const RevCoef &rc, const Stream &s,
+                                     uint32_t pid, Particle &q, int64_t m, int64_t m_chk,
+                                     const RevCtx &cx, const Stage<SCHEME> &R, Stage<SCHEME> &W,
+                                     Rev &r)
+{
+    constexpr int kB = Stage<SCHEME>::B;
+    if (m == m_chk) {
+        rev_window<SCHEME, VFORM, true>(k, rc, R, m * kB, kB, cx, 0.0f, r);
+        rec_window<SCHEME>(k, s, pid, q, (m - 1) * kB, kB, W);
+        return;
+    }
+    const float add_w = (VFORM && m * kB >= cx.wb) ? cx.invW : 0.0f;
+    Noise4 z;
+    float xb = q.xf + k.phi;
+#pragma unroll
+    for (int t = 0; t < kB; ++t) {
+        rec_slot<SCHEME>(k, s, pid, q, xb, z, (m - 1) * kB, t, W);
+        const int u = kB - 1 - t;
+        rev_slot<SCHEME, VFORM, false>(k, rc, R, u, m * kB + u, cx, add_w, r);
+    }
+}
+
+// Reverse a whole staged window with no recomputation beside it.
+template <int SCHEME, int VFORM>
+__device__ __forceinline__ void last_window(const Coef &k, const RevCoef &rc, int64_t m,
+                                            int64_t m_chk, const RevCtx &cx,
+                                            const Stage<SCHEME> &R, Rev &r)
+{
+    constexpr int kB = Stage<SCHEME>::B;
+    if (m == m_chk) {
+        rev_window<SCHEME, VFORM, true>(k, rc, R, m * kB, kB, cx, 0.0f, r);
+    } else {
+        const float add_w = (VFORM && m * kB >= cx.wb) ? cx.invW : 0.0f;
+        rev_window<SCHEME, VFORM, false>(k, rc, R, m * kB, kB, cx, add_w, r);
+    }
 }
 
 __device__ __forceinline__ void flush(Rev &r, double (&A64)[kSums])
@@ -379,14 +453,17 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
     const Stream s{a.k0, a.k1, (uint32_t)L.set};
     const uint32_t pid[1] = {(uint32_t)L.i};
     const int64_t wb = a.S - a.W;
-    const float jscale = (float)(1.0 / ((double)a.W * a.dt));
-    const float invW = (float)(1.0 / (double)a.W);
-    const float rho = a.rho;
+    RevCtx cx;
+    cx.wb = wb;
+    cx.jscale = (float)(1.0 / ((double)a.W * a.dt));
+    cx.invW = (float)(1.0 / (double)a.W);
+    cx.rho = a.rho;
+    const int64_t m_chk = wb >= 1 ? (wb - 1) / kStage : -1;  // sub-window holding step wb - 1
     // exact form: J = (x_S - x_{S-W}) / (W dt); decayed form: J = (1/W) sum_{n >= S-W} v_n, which
     // is the same function of the Euler-Maruyama path, with each v_n's sensitivity damped by rho
     // per step of look-back
     Rev r;
-    r.lx = VFORM ? 0.0f : jscale;
+    r.lx = VFORM ? 0.0f : cx.jscale;
     r.lv = r.le = 0.0f;
 #pragma unroll
     for (int i = 0; i < kSums; ++i)
@@ -415,22 +492,13 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             ck = get_state(a.ckpt + (size_t)(j - 1) * 7 * N, N, L.g);
 
         Stage<SCHEME> SA, SB;
-        Noise4 z;
         Particle q = p[0];
         int64_t m = m1;
         const int hi1 = (int)(s1 - m1 * kStage);
         if (hi1 < kStage) {
             // the run's final sub-window is shorter: recompute and reverse it on its own
-            float xb = q.xf + k.phi;
-#pragma unroll
-            for (int t = 0; t < kStage; ++t)
-                if (t < hi1)
-                    rec_slot<SCHEME>(k, s, pid[0], q, xb, z, m1 * kStage, t, SA);
-#pragma unroll
-            for (int t = kStage - 1; t >= 0; --t)
-                if (t < hi1)
-                    rev_slot<SCHEME, VFORM>(k, rc, SA, t, m1 * kStage + t, wb, jscale, invW,
-                                            rho, r);
+            rec_window<SCHEME>(k, s, pid[0], q, m1 * kStage, hi1, SA);
+            rev_window<SCHEME, VFORM, true>(k, rc, SA, m1 * kStage, hi1, cx, 0.0f, r);
             flush(r, A64);
             if (m1 == m0)
                 continue;
@@ -438,63 +506,34 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             q = get_state(sub + (size_t)(m - m0) * 7 * N, N, L.g);
         }
         // prologue: stage window m into SA
-        {
-            float xb = q.xf + k.phi;
-#pragma unroll
-            for (int t = 0; t < kStage; ++t)
-                rec_slot<SCHEME>(k, s, pid[0], q, xb, z, m * kStage, t, SA);
-        }
+        rec_window<SCHEME>(k, s, pid[0], q, m * kStage, kStage, SA);
         Particle nxt;
         if (m > m0)
             nxt = get_state(sub + (size_t)(m - 1 - m0) * 7 * N, N, L.g);
         // steady state, two windows per trip with the staging buffers swapping roles
         for (;;) {
             if (m == m0) {
-#pragma unroll
-                for (int t = kStage - 1; t >= 0; --t)
-                    rev_slot<SCHEME, VFORM>(k, rc, SA, t, m * kStage + t, wb, jscale, invW,
-                                            rho, r);
+                last_window<SCHEME, VFORM>(k, rc, m, m_chk, cx, SA, r);
                 flush(r, A64);
                 break;
             }
-            {
-                q = nxt;
-                if (m - 1 > m0)
-                    nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
-                float xb = q.xf + k.phi;
-#pragma unroll
-                for (int t = 0; t < kStage; ++t) {
-                    rec_slot<SCHEME>(k, s, pid[0], q, xb, z, (m - 1) * kStage, t, SB);
-                    const int u = kStage - 1 - t;
-                    rev_slot<SCHEME, VFORM>(k, rc, SA, u, m * kStage + u, wb, jscale, invW,
-                                            rho, r);
-                }
-                flush(r, A64);
-                --m;
-            }
+            q = nxt;
+            if (m - 1 > m0)
+                nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
+            trip<SCHEME, VFORM>(k, rc, s, pid[0], q, m, m_chk, cx, SA, SB, r);
+            flush(r, A64);
+            --m;
             if (m == m0) {
-#pragma unroll
-                for (int t = kStage - 1; t >= 0; --t)
-                    rev_slot<SCHEME, VFORM>(k, rc, SB, t, m * kStage + t, wb, jscale, invW,
-                                            rho, r);
+                last_window<SCHEME, VFORM>(k, rc, m, m_chk, cx, SB, r);
                 flush(r, A64);
                 break;
             }
-            {
-                q = nxt;
-                if (m - 1 > m0)
-                    nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
-                float xb = q.xf + k.phi;
-#pragma unroll
-                for (int t = 0; t < kStage; ++t) {
-                    rec_slot<SCHEME>(k, s, pid[0], q, xb, z, (m - 1) * kStage, t, SA);
-                    const int u = kStage - 1 - t;
-                    rev_slot<SCHEME, VFORM>(k, rc, SB, u, m * kStage + u, wb, jscale, invW,
-                                            rho, r);
-                }
-                flush(r, A64);
-                --m;
-            }
+            q = nxt;
+            if (m - 1 > m0)
+                nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
+            trip<SCHEME, VFORM>(k, rc, s, pid[0], q, m, m_chk, cx, SB, SA, r);
+            flush(r, A64);
+            --m;
         }
     }
     // dJ/d(U0, a, D, d2, q, c, gamma0, F0) from the sums (FP64)
