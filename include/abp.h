@@ -67,6 +67,16 @@ typedef struct abp_run {
     uint64_t seed;      /* Philox key */
     uint32_t set_id;    /* Philox counter word 2 (parameter-set index) */
     int32_t scheme;     /* abp_scheme */
+    /* Time-accumulated histogram of x mod 1 (the particle density the paper displays while the
+     * ensemble runs, Sec. 2), single-set integrator only. hist_stride = 0: off. hist_stride > 0:
+     * after every absolute step index n with step0 < n <= step0 + n_steps and n a multiple of
+     * hist_stride, each particle's x_n mod 1 is counted into d_hist_acc[hist_bins] (bins as for
+     * the final-position histogram). Counts are added to what d_hist_acc holds, so chunked calls
+     * accumulate like one call; the caller zeroes it. hist_bins: power of two <= 4096. */
+    int64_t hist_stride;
+    uint64_t *d_hist_acc;  /* device, 8-byte aligned */
+    int32_t hist_bins;
+    int32_t pad;
 } abp_run;
 /* step0 + n_steps must not exceed 2^34 (the block counter n/4 is one 32-bit word). */
 
@@ -120,6 +130,7 @@ size_t abp_reduce_workspace_bytes(int64_t n, int32_t n_bins);
  *        window displacement and its square, and the histogram of x mod 1 (n_bins bins), are
  *        written to d_ws (ws_bytes >= abp_reduce_workspace_bytes(n, n_bins)); abp_reduce turns
  *        them into results. Requires a window (win_begin >= 0, win_begin <= step0 + n_steps).
+ *  r->hist_stride > 0: the time-accumulated histogram is added to r->d_hist_acc as well.
  *  tune: NULL = default launch shape. */
 abp_status abp_integrate(const abp_params *p, const abp_run *r, const abp_state *s,
                          const abp_state *snap, void *d_ws, size_t ws_bytes, int32_t n_bins,

@@ -172,6 +172,28 @@ def reduce(x_snap, x_end, window_time: float, n_bins: int = 256):
     return float(out[0]), float(out[1]), hist[:n_bins]
 
 
+def occupancy(params: dict | None, x, v, e, n_steps: int, stride: int, n_bins: int = 256,
+              dt: float = 1e-3, scheme: int = EM, seed: int = 42, set_id: int = 0,
+              step0: int = 0, ids=None):
+    """Time-accumulated histogram of x mod 1: the particle density displayed while the ensemble
+    runs (Sec. 2). By definition the sum, over the absolute steps n in (step0, step0 + n_steps]
+    that are multiples of `stride`, of the histogram of the positions x_n; computed here as
+    integrate to each such n, then reduce's histogram. Returns (hist, x, v, e) at the end."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    v = np.array(v, dtype=np.float64, copy=True)
+    e = np.array(e, dtype=np.float64, copy=True)
+    acc = np.zeros(n_bins, dtype=np.uint64)
+    end = step0 + n_steps
+    at = step0
+    for target in range((step0 // stride + 1) * stride, end + 1, stride):
+        x, v, e, _, _ = integrate(params, x, v, e, target - at, dt, scheme, seed, set_id, at,
+                                  ids=ids)
+        at = target
+        acc += reduce(x, x, 1.0, n_bins)[2]
+    x, v, e, _, _ = integrate(params, x, v, e, end - at, dt, scheme, seed, set_id, at, ids=ids)
+    return acc, x, v, e
+
+
 def rk4(params: dict | None, x, v, e, n_steps: int, dt: float):
     x = np.array(x, dtype=np.float64, copy=True)
     v = np.array(v, dtype=np.float64, copy=True)

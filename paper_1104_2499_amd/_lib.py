@@ -25,7 +25,9 @@ class AbpParams(ctypes.Structure):
 class AbpRun(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("n_steps", ctypes.c_int64), ("step0", ctypes.c_int64),
                 ("win_begin", ctypes.c_int64), ("seed", ctypes.c_uint64),
-                ("set_id", ctypes.c_uint32), ("scheme", ctypes.c_int32)]
+                ("set_id", ctypes.c_uint32), ("scheme", ctypes.c_int32),
+                ("hist_stride", ctypes.c_int64), ("d_hist_acc", ctypes.c_void_p),
+                ("hist_bins", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class AbpState(ctypes.Structure):

@@ -151,10 +151,17 @@ def reduce_workspace(n: int, n_bins: int, device="cuda") -> torch.Tensor:
 def integrate(state: State, n_steps: int, params: dict | None = None, dt: float = 1e-3,
               scheme="em", seed: int = 42, set_id: int = 0, step0: int = 0, win_begin: int = -1,
               snap: State | None = None, ws: torch.Tensor | None = None, n_bins: int = 0,
-              tune=None, stream=None) -> None:
-    """Advance `state` in place (abp_integrate). With `ws`, also leave the reduction partials."""
+              tune=None, stream=None, hist_stride: int = 0,
+              hist_acc: torch.Tensor | None = None) -> None:
+    """Advance `state` in place (abp_integrate). With `ws`, also leave the reduction partials.
+    hist_stride > 0 adds x mod 1 at every absolute step that is a multiple of it to hist_acc
+    (int64 [bins] on the device, holding u64 counts; the caller zeroes it)."""
     p = make_params(params)
     r = _lib.AbpRun(dt, n_steps, step0, win_begin, seed, set_id, scheme_id(scheme))
+    if hist_stride:
+        if hist_acc is None or hist_acc.dtype != torch.int64 or not hist_acc.is_contiguous():
+            raise ValueError("hist_stride needs hist_acc: a contiguous int64 device tensor")
+        r.hist_stride, r.d_hist_acc, r.hist_bins = hist_stride, hist_acc.data_ptr(), hist_acc.numel()
     s = state.abi()
     sn = snap.abi() if snap is not None else None
     t = make_tuning(tune)
@@ -188,24 +195,27 @@ class Result:
     hist: torch.Tensor
     state: State
     snap: State
+    occupancy: torch.Tensor | None = None  # time-accumulated histogram (hist_stride > 0)
 
 
 def run(params: dict | None = None, n: int = 1024, steps: int = 10_000, window: int | None = None,
         dt: float = 1e-3, scheme="em", seed: int = 42, bins: int = 256, set_id: int = 0,
-        tune=None, device="cuda", stream=None) -> Result:
+        tune=None, device="cuda", stream=None, hist_stride: int = 0) -> Result:
     """Initial condition, `steps` steps, window mean velocity over the last `window` steps
-    (default: the last half) and the histogram of the final x mod 1."""
+    (default: the last half) and the histogram of the final x mod 1; with hist_stride > 0 also
+    the histogram of x mod 1 accumulated every hist_stride steps (bins bins)."""
     window = steps // 2 if window is None else window
     if not 1 <= window <= steps:
         raise ValueError("need 1 <= window <= steps")
     st = init_state(n, seed, set_id, device=device, stream=stream)
     snap = State.empty(n, device)
     ws = reduce_workspace(n, bins, device)
+    occ = torch.zeros(bins, dtype=torch.int64, device=device) if hist_stride else None
     integrate(st, steps, params, dt, scheme, seed, set_id, 0, steps - window, snap, ws, bins,
-              tune, stream)
+              tune, stream, hist_stride, occ)
     out, hist = reduce(ws, n, bins, window * dt, stream)
     o = out.cpu()
-    return Result(float(o[0]), float(o[1]), hist, st, snap)
+    return Result(float(o[0]), float(o[1]), hist, st, snap, occ)
 
 
 @dataclass

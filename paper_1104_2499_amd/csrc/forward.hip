@@ -5,6 +5,8 @@
 //   double part[n_tiles][2]   sums of delta and delta^2 over each 64-particle tile, delta = window
 //                             displacement in FP64; tile t = particles [64 t, 64 t + 64)
 //   uint32 hist[n_bins]       counts of x mod 1 (integer atomics: order-free, hence deterministic)
+// The optional time-accumulated histogram goes to a caller-owned u64 array instead: each block
+// counts into LDS and adds its counts once at the end.
 // Tiles do not depend on the launch shape, and abp_reduce adds them in a fixed order, so the
 // results are bit-identical for every tuning.
 #include "reduce.hpp"
@@ -56,6 +58,9 @@ struct FwdArgs {
     int64_t step0, n_steps, win_begin;
     double *part;    // null: no reduction in this call
     uint32_t *hist;
+    int64_t acc_stride;  // > 0: time-accumulated histogram every acc_stride absolute steps
+    uint64_t *acc;       // [acc_bins]
+    int32_t acc_bins;
 };
 
 inline size_t hist_offset(int64_t n)
@@ -63,62 +68,100 @@ inline size_t hist_offset(int64_t n)
     return align_up((size_t)n_tiles(n) * 2 * sizeof(double), 256);
 }
 
-template <int SCHEME, int PPL, int UNROLL>
+// Advance the lane's particles to absolute step `stop`; with the time-accumulated histogram
+// (COUNTED), stop after every absolute step that is a multiple of acc_stride and count x mod 1
+// into loc.
+template <int SCHEME, int PPL, int UNROLL, bool COUNTED>
+__device__ __forceinline__ void advance_counted(const FwdArgs &a, const uint32_t (&pid)[PPL],
+                                                Particle (&p)[PPL], const bool (&live)[PPL],
+                                                int64_t &step, int64_t stop, uint32_t *loc)
+{
+    if constexpr (COUNTED) {
+        for (int64_t nxt = (step / a.acc_stride + 1) * a.acc_stride; nxt <= stop;
+             nxt += a.acc_stride) {
+            advance<SCHEME, PPL, UNROLL>(a.k, a.s, pid, p, step, nxt);
+#pragma unroll
+            for (int q = 0; q < PPL; ++q)
+                if (live[q])
+                    atomicAdd(&loc[hist_bin(position64(p[q].cell, p[q].xf, p[q].lx),
+                                            a.acc_bins)], 1u);
+        }
+    }
+    advance<SCHEME, PPL, UNROLL>(a.k, a.s, pid, p, step, stop);
+}
+
+template <int SCHEME, int PPL, int UNROLL, bool COUNTED>
 __global__ __launch_bounds__(256) void k_integrate(FwdArgs a)
 {
+    extern __shared__ uint32_t loc[];  // [acc_bins] when COUNTED
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t base = wave * 64 * PPL;
     const int64_t n = a.st.n;
-    if (base >= n)
-        return;  // wavefront-uniform
-
-    Particle p[PPL];
-    uint32_t pid[PPL];
-    bool live[PPL];
-#pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-        const int64_t i = base + 64 * q + lane;
-        live[q] = i < n;
-        pid[q] = a.id0 + (uint32_t)i;
-        if (live[q]) {
-            p[q] = a.st.load(i);
-        } else {
-            p[q].cell = 0;
-            p[q].xf = p[q].v = p[q].e = 0.0f;
-            p[q].lx = p[q].lv = p[q].le = 0.0f;
-        }
+    if (base >= n && !COUNTED)
+        return;  // wavefront-uniform; with COUNTED every wave reaches the block barriers
+    if constexpr (COUNTED) {
+        for (int b = threadIdx.x; b < a.acc_bins; b += blockDim.x)
+            loc[b] = 0u;
+        __syncthreads();
     }
 
-    const int64_t end = a.step0 + a.n_steps;
-    int64_t step = a.step0;
-    double xs[PPL];
-    const bool snap_here = a.win_begin >= a.step0 && a.win_begin <= end;
-    if (snap_here) {
-        advance<SCHEME, PPL, UNROLL>(a.k, a.s, pid, p, step, a.win_begin);
+    if (base < n) {
+        Particle p[PPL];
+        uint32_t pid[PPL];
+        bool live[PPL];
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-            xs[q] = position64(p[q].cell, p[q].xf, p[q].lx);
+            const int64_t i = base + 64 * q + lane;
+            live[q] = i < n;
+            pid[q] = a.id0 + (uint32_t)i;
+            if (live[q]) {
+                p[q] = a.st.load(i);
+            } else {
+                p[q].cell = 0;
+                p[q].xf = p[q].v = p[q].e = 0.0f;
+                p[q].lx = p[q].lv = p[q].le = 0.0f;
+            }
+        }
+
+        const int64_t end = a.step0 + a.n_steps;
+        int64_t step = a.step0;
+        double xs[PPL];
+        const bool snap_here = a.win_begin >= a.step0 && a.win_begin <= end;
+        if (snap_here) {
+            advance_counted<SCHEME, PPL, UNROLL, COUNTED>(a, pid, p, live, step, a.win_begin, loc);
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                xs[q] = position64(p[q].cell, p[q].xf, p[q].lx);
+                if (live[q])
+                    a.snap.store(base + 64 * q + lane, p[q]);
+            }
+        }
+        advance_counted<SCHEME, PPL, UNROLL, COUNTED>(a, pid, p, live, step, end, loc);
+
+#pragma unroll
+        for (int q = 0; q < PPL; ++q)
             if (live[q])
-                a.snap.store(base + 64 * q + lane, p[q]);
+                a.st.store(base + 64 * q + lane, p[q]);
+
+        if (a.part) {
+            double xe[PPL];
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                xe[q] = position64(p[q].cell, p[q].xf, p[q].lx);
+                if (!snap_here)
+                    xs[q] = live[q] ? a.snap.x64(base + 64 * q + lane) : 0.0;
+            }
+            reduce_tiles<PPL>(xe, xs, live, base / 64, n, lane, a.n_bins, a.part, a.hist);
         }
     }
-    advance<SCHEME, PPL, UNROLL>(a.k, a.s, pid, p, step, end);
 
-#pragma unroll
-    for (int q = 0; q < PPL; ++q)
-        if (live[q])
-            a.st.store(base + 64 * q + lane, p[q]);
-
-    if (a.part) {
-        double xe[PPL];
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            xe[q] = position64(p[q].cell, p[q].xf, p[q].lx);
-            if (!snap_here)
-                xs[q] = live[q] ? a.snap.x64(base + 64 * q + lane) : 0.0;
-        }
-        reduce_tiles<PPL>(xe, xs, live, base / 64, n, lane, a.n_bins, a.part, a.hist);
+    if constexpr (COUNTED) {
+        __syncthreads();
+        for (int b = threadIdx.x; b < a.acc_bins; b += blockDim.x)
+            if (loc[b])
+                atomicAdd(reinterpret_cast<unsigned long long *>(&a.acc[b]),
+                          (unsigned long long)loc[b]);
     }
 }
 
@@ -149,19 +192,25 @@ __global__ __launch_bounds__(64) void k_finalize(const double *part, int64_t nti
         hist64[b] = hist32[b];
 }
 
-template <int SCHEME, int PPL, int UNROLL>
+template <int SCHEME, int PPL, int UNROLL, bool COUNTED = false>
 static void launch_integrate(const FwdArgs &a, int block, hipStream_t st)
 {
     const int64_t waves = (a.st.n + 64 * PPL - 1) / (64 * PPL);
     const int64_t threads = waves * 64;
     const unsigned grid = (unsigned)((threads + block - 1) / block);
-    hipLaunchKernelGGL((k_integrate<SCHEME, PPL, UNROLL>), dim3(grid), dim3(block), 0, st, a);
+    const size_t lds = COUNTED ? sizeof(uint32_t) * (size_t)a.acc_bins : 0;
+    hipLaunchKernelGGL((k_integrate<SCHEME, PPL, UNROLL, COUNTED>), dim3(grid), dim3(block), lds,
+                       st, a);
 }
 
+// The time-histogram variant runs one particle per lane and no unrolling (its results, like
+// every variant's, do not depend on the launch shape); only the block size is taken from tuning.
 template <int SCHEME>
 static void dispatch_integrate(const FwdArgs &a, const Shape &sh, hipStream_t st)
 {
-    if (sh.ppl == 1) {
+    if (a.acc_stride > 0) {
+        launch_integrate<SCHEME, 1, 1, true>(a, sh.block, st);
+    } else if (sh.ppl == 1) {
         if (sh.unroll == 1)
             launch_integrate<SCHEME, 1, 1>(a, sh.block, st);
         else
@@ -213,7 +262,10 @@ extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const
         return ABP_E_ARG;
     if (!(r->dt > 0.0) || !is_finite(r->dt) || r->n_steps < 0 || r->step0 < 0 ||
         r->n_steps > kMaxStepIndex || r->step0 + r->n_steps > kMaxStepIndex || r->win_begin < -1 ||
-        (r->scheme != ABP_EM && r->scheme != ABP_HEUN))
+        (r->scheme != ABP_EM && r->scheme != ABP_HEUN) || r->hist_stride < 0)
+        return ABP_E_ARG;
+    if (r->hist_stride > 0 && (r->hist_bins < 1 || !bins_ok(r->hist_bins) || !r->d_hist_acc ||
+                               !aligned(r->d_hist_acc, 8)))
         return ABP_E_ARG;
     const int64_t end = r->step0 + r->n_steps;
     const bool snap_write = r->win_begin >= r->step0 && r->win_begin <= end;
@@ -243,6 +295,11 @@ extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const
     a.step0 = r->step0;
     a.n_steps = r->n_steps;
     a.win_begin = r->win_begin;
+    if (r->hist_stride > 0) {
+        a.acc_stride = r->hist_stride;
+        a.acc = r->d_hist_acc;
+        a.acc_bins = r->hist_bins;
+    }
     if (reduce) {
         a.part = reinterpret_cast<double *>(d_ws);
         a.hist = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(d_ws) + hist_offset(s->n));

@@ -3,7 +3,9 @@
 load_force_curve(): mean drift velocity <v> against the load force F0, one parameter set per F0
 value, all sets in one persistent launch (the use case behind Fig. 2: in Sec. 2 each work item is
 one value of the load force, and all of them run at once). The load power -F0 <v> is returned
-beside it (positive when the particles move against the load).
+beside it (positive when the particles move against the load), and the depot efficiency
+-F0 <v> / q: the useful power per unit of the energy flux q that feeds the depot, Eq. (1) (the
+paper names the efficiency question but leaves its definition to the works it cites).
 
 scaling(): time of one integration call against the number of work items, repeated R times with
 the first repeats discarded (Sec. 3 runs 20 and averages the last 15), for several step counts
@@ -35,7 +37,9 @@ def load_force_curve(F0, params: dict | None = None, n: int = 4096, steps: int =
     r = api.sweep(table, np.full(F0.size, n, np.int32), np.full(F0.size, steps, np.int64),
                   np.full(F0.size, window, np.int64), scheme=scheme, seed=seed, bins=bins,
                   tune=tune)
-    return {"F0": F0, "mean_v": r.mean_v, "stderr": r.stderr, "load_power": -F0 * r.mean_v}
+    power = -F0 * r.mean_v
+    return {"F0": F0, "mean_v": r.mean_v, "stderr": r.stderr, "load_power": power,
+            "efficiency": power / base["q"]}
 
 
 def _time_call(n: int, steps: int, scheme: str, state, snap, ws, stream) -> float:
@@ -88,9 +92,10 @@ if __name__ == "__main__":
         t0 = time.perf_counter()
         out = load_force_curve(F0, steps=20_000 if args.quick else 100_000)
         secs = time.perf_counter() - t0
-        for f, v, s, p in zip(out["F0"], out["mean_v"], out["stderr"], out["load_power"]):
+        for f, v, s, p, eta in zip(out["F0"], out["mean_v"], out["stderr"], out["load_power"],
+                                   out["efficiency"]):
             print(json.dumps({"F0": round(float(f), 4), "mean_v": float(v), "stderr": float(s),
-                              "load_power": float(p)}))
+                              "load_power": float(p), "efficiency": float(eta)}))
         print(json.dumps({"seconds": secs}))
     else:
         sizes = [2 ** k for k in range(0, 21)]

@@ -96,6 +96,10 @@ def test_integrate_rejects_bad_arguments_without_a_device(lib):
     win = _lib.AbpRun(1e-3, 100, 0, 50, 42, 0, 0)
     assert call(r=win, ws=ws, wsb=1 << 20, bins=100, snap=_state()) == E_ARG
     assert call(r=win, ws=ws, wsb=16, bins=256, snap=_state()) == _lib.ABP_E_WORKSPACE
+    # time-accumulated histogram: negative stride, bad bins, missing or misaligned array
+    for stride, ptr, bins_ in ((-1, 0x10000, 64), (10, 0x10000, 0), (10, 0x10000, 48),
+                               (10, 0x10000, 8192), (10, 0, 64), (10, 0x10004, 64)):
+        assert call(r=_lib.AbpRun(1e-3, 100, 0, -1, 42, 0, 0, stride, ptr, bins_)) == E_ARG
     assert call(tune=_lib.AbpTuning(96, 1, 1, 0)) == E_ARG
     assert call(tune=_lib.AbpTuning(256, 3, 1, 0)) == E_ARG
     assert call(tune=_lib.AbpTuning(256, 1, 4, 0)) == E_ARG

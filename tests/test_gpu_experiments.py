@@ -17,6 +17,7 @@ def test_load_force_curve_passive_limit(gpu):
     assert abs(v[2]) <= 4 * se[2]
     assert np.all(np.diff(v) > 0)
     np.testing.assert_allclose(out["load_power"], -F0 * v)
+    np.testing.assert_allclose(out["efficiency"], -F0 * v / 1.0)  # q = 1 in the base parameters
 
 
 def test_load_force_curve_sets_equal_single_runs(gpu):

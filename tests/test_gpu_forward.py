@@ -276,3 +276,60 @@ def test_full_size_heun_sampled(gpu, orc):
     mean, se, _ = orc.reduce(xs, x, window * 1e-3, 256)
     assert abs(big.mean_v - mean) <= 4 * np.hypot(big.stderr, se)
     assert int(_np(big.hist).sum()) == n
+
+
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_time_histogram(gpu, orc, scheme):
+    """Time-accumulated histogram of x mod 1 (every 100 steps over 1000 steps, 1000 particles,
+    64 bins): (i) equal bit for bit to the sum of the final-position histograms of runs stopped
+    at each sample step; (ii) chunked calls accumulate like one call; (iii) against the FP64
+    oracle, counts differ only by particles whose trajectories differ (here < 1e-3 of all)."""
+    from paper_1104_2499_amd import api
+
+    n, S, stride, bins, seed = 1000, 1000, 100, 64, 21
+    r = api.run(BASE, n=n, steps=S, window=S, scheme=scheme, seed=seed, bins=bins,
+                hist_stride=stride)
+    occ = _np(r.occupancy)
+    assert occ.sum() == n * (S // stride)
+    # (i) by definition, from plain runs and final-position histograms
+    st = api.init_state(n, seed)
+    snap = api.State.empty(n)
+    ws = api.reduce_workspace(n, bins)
+    want = np.zeros(bins, dtype=np.int64)
+    for k in range(S // stride):
+        api.integrate(st, stride, BASE, scheme=scheme, seed=seed, step0=k * stride,
+                      win_begin=k * stride, snap=snap, ws=ws, n_bins=bins)
+        want += _np(api.reduce(ws, n, bins, 1.0)[1])
+    np.testing.assert_array_equal(occ, want)
+    # (ii) chunked (boundaries off the sample grid and on it)
+    st = api.init_state(n, seed)
+    acc = torch.zeros(bins, dtype=torch.int64, device="cuda")
+    for a, b in ((0, 370), (370, 400), (400, 1000)):
+        api.integrate(st, b - a, BASE, scheme=scheme, seed=seed, step0=a, hist_stride=stride,
+                      hist_acc=acc)
+    np.testing.assert_array_equal(_np(acc), occ)
+    # (iii) oracle
+    x0, v0, e0 = orc.init_state(n, seed)
+    h, _, _, _ = orc.occupancy(BASE, x0, v0, e0, S, stride, n_bins=bins, seed=seed,
+                               scheme=0 if scheme == "em" else 1)
+    assert np.abs(occ - h.astype(np.int64)).sum() <= 1e-3 * occ.sum()
+
+
+def test_time_histogram_edges(gpu):
+    """No sample step in range: nothing is added; the counts add to what the array holds;
+    invalid arguments are rejected before any launch."""
+    from paper_1104_2499_amd import api
+
+    st = api.init_state(300, 3)
+    acc = torch.full((16,), 5, dtype=torch.int64, device="cuda")
+    api.integrate(st, 99, BASE, seed=3, step0=0, hist_stride=100, hist_acc=acc)
+    assert _np(acc).tolist() == [5] * 16
+    api.integrate(st, 1, BASE, seed=3, step0=99, hist_stride=100, hist_acc=acc)
+    assert _np(acc).sum() == 5 * 16 + 300
+    with pytest.raises(api.AbpError, match="ABP_E_ARG"):
+        api.integrate(st, 10, BASE, seed=3, hist_stride=-1, hist_acc=acc)
+    with pytest.raises(api.AbpError, match="ABP_E_ARG"):
+        api.integrate(st, 10, BASE, seed=3, hist_stride=5,
+                      hist_acc=torch.zeros(12, dtype=torch.int64, device="cuda"))
+    with pytest.raises(ValueError):
+        api.integrate(st, 10, BASE, seed=3, hist_stride=5, hist_acc=None)

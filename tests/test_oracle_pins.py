@@ -248,6 +248,43 @@ def test_passive_ratchet_zero_current_and_boltzmann(orc):
     assert edges.size == 33
 
 
+def test_occupancy_time_average_is_boltzmann(orc):
+    """The time-accumulated histogram of passive particles (d2 = F0 = 0) after a burn-in follows
+    the same Boltzmann law as the snapshot: total-variation distance below 0.015 with 4096
+    particles x 30 samples (measured 0.006; the histogram shifted by one bin gives 0.028, a flat
+    one 0.125)."""
+    n, dt = 4096, 1e-3
+    U0, a, D, g = 0.2, 0.25, 0.5, 1.0
+    p = dict(U0=U0, a=a, D=D, gamma0=g, d2=0.0, F0=0.0)
+    x, v, e = orc.init_state(n, 8)
+    x, v, e, _, _ = orc.integrate(p, x, v, e, 5000, dt=dt, seed=8)
+    occ, _, _, _ = orc.occupancy(p, x, v, e, 15000, 500, n_bins=32, dt=dt, seed=8, step0=5000)
+    assert occ.sum() == n * 30
+    fine = np.linspace(0, 1, 32 * 64 + 1)[:-1] + 0.5 / (32 * 64)
+    w = np.exp(-g * _U(fine, U0, a) / D).reshape(32, 64).sum(axis=1)
+    tv = 0.5 * np.abs(occ / occ.sum() - w / w.sum()).sum()
+    assert tv < 0.015, tv
+
+
+def test_occupancy_definition_cases(orc):
+    """One sample at the end equals the final-position histogram; the sample count is the number
+    of multiples of the stride in (step0, step0 + n_steps]; sampling leaves the state unchanged;
+    chunked accumulation equals one call."""
+    x0, v0, e0 = orc.init_state(300, 4)
+    occ, x, v, e = orc.occupancy(None, x0, v0, e0, 400, 400, n_bins=64, seed=4)
+    xf, vf, ef, _, _ = orc.integrate(None, x0, v0, e0, 400, seed=4)
+    np.testing.assert_array_equal(occ, orc.reduce(xf, xf, 1.0, 64)[2])
+    for a_, b_ in zip((x, v, e), (xf, vf, ef)):
+        np.testing.assert_array_equal(a_, b_)
+    occ, _, _, _ = orc.occupancy(None, x0, v0, e0, 100, 10, n_bins=16, seed=4, step0=7)
+    assert occ.sum() == 300 * 10
+    full, xa, _, _ = orc.occupancy(None, x0, v0, e0, 300, 20, n_bins=64, seed=4)
+    h1, x1, v1, e1 = orc.occupancy(None, x0, v0, e0, 130, 20, n_bins=64, seed=4)
+    h2, x2, _, _ = orc.occupancy(None, x1, v1, e1, 170, 20, n_bins=64, seed=4, step0=130)
+    np.testing.assert_array_equal(full, h1 + h2)
+    np.testing.assert_array_equal(xa, x2)
+
+
 def test_em_displacement_equals_time_average(orc):
     """For EM, x_S - x_(S-W) = dt * sum of v_n over the window exactly (x uses the old v)."""
     x, v, e = orc.init_state(256, 42)
