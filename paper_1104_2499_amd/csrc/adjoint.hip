@@ -13,7 +13,10 @@
 // Euler-Maruyama, 8 for Heun; K is rounded up to a multiple of 16); then, for each sub-window in
 // reverse, it restores the sub-checkpoint, recomputes the sub-window while staging the values the
 // reverse step needs (cos and sin of the phase, v, e at every point where the drift is evaluated,
-// and sigma*xi) in registers, and runs the adjoint recursion backwards over it. The recomputation reproduces the
+// and sigma*xi) in registers, and runs the adjoint recursion backwards over it. When the segment's
+// noise fits in LDS (K - B steps x 64 lanes x 4 bytes per wavefront, four wavefronts per CU),
+// level 1 keeps each sigma*xi it draws there and the staged recomputation reads it back instead of
+// running Philox and Box-Muller a second time. The recomputation reproduces the
 // forward bits exactly (the integrator's state is resumable mid-block), so the result does not
 // depend on K. Per-step gradient terms are summed in FP32 within each absolute B-step window and
 // in FP64 across windows (that grouping does not depend on K either); tiles of 64 particles and
@@ -64,6 +67,7 @@ struct AdjArgs {
     int32_t n_sets;
     float rho;        // per-step decay of the adjoint (1 = exact gradient)
     int32_t vform;    // 1: the loss enters as (1/W) sum of v_n over the window (used with rho < 1)
+    int32_t z_slots;  // steps of noise each lane keeps in LDS (K - B), when that variant runs
 };
 
 constexpr int kAlign = 16;    // checkpoint intervals are multiples of this
@@ -206,16 +210,22 @@ struct Stage<1> {
     float c[B], s[B], v[B], e[B], ct[B], st[B], vt[B], et[B], z[B];
 };
 
-// Recompute slot t of a sub-window (absolute step base + t), staging its inputs. The staged
+// Recompute slot t of a sub-window (absolute step base + t), staging its inputs. The noise is
+// regenerated or (FROM_LDS) read from the lane's LDS copy zl[64 t] kept by level 1. The staged
 // predictor repeats step_heun's own expressions, so it holds the values that step saw.
-template <int SCHEME>
+template <int SCHEME, bool FROM_LDS>
 __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_t pid, Particle &q,
                                          float &xb, Noise4 &z, int64_t base, int t,
-                                         Stage<SCHEME> &B)
+                                         Stage<SCHEME> &B, const float *zl)
 {
-    if ((t & 3) == 0)
-        z = noise_block((uint32_t)((base + t) >> 2), pid, s.set, s.k0, s.k1, k.bm);
-    const float zs = z.z[t & 3];
+    float zs;
+    if constexpr (FROM_LDS) {
+        zs = zl[64 * t];
+    } else {
+        if ((t & 3) == 0)
+            z = noise_block((uint32_t)((base + t) >> 2), pid, s.set, s.k0, s.k1, k.bm);
+        zs = z.z[t & 3];
+    }
     const float xc = xb + q.lx, vc = q.v + q.lv, ec = q.e + q.le;
     B.c[t] = __builtin_amdgcn_cosf(xc);
     B.s[t] = __builtin_amdgcn_sinf(xc);
@@ -237,6 +247,26 @@ __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_
     if ((t & 3) == 3) {
         end_block(q);
         xb = q.xf + k.phi;
+    }
+}
+
+// Level 1 over one whole sub-window starting at absolute step base: the same arithmetic as
+// advance(), keeping each sigma*xi in the lane's LDS copy zw[64 t].
+template <int SCHEME>
+__device__ __forceinline__ void level1_window(const Coef &k, const Stream &s, uint32_t pid,
+                                              Particle &p, int64_t base, float *zw)
+{
+    constexpr int kB = Stage<SCHEME>::B;
+#pragma unroll
+    for (int b = 0; b < kB / 4; ++b) {
+        const Noise4 z = noise_block((uint32_t)((base >> 2) + b), pid, s.set, s.k0, s.k1, k.bm);
+        const float xb = p.xf + k.phi;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            zw[64 * (4 * b + j)] = z.z[j];
+            step<SCHEME>(k, p, xb, z.z[j]);
+        }
+        end_block(p);
     }
 }
 
@@ -372,30 +402,31 @@ __device__ __forceinline__ void rev_window(const Coef &k, const RevCoef &rc,
 
 // Recompute the first `hi` slots of the sub-window starting at absolute step base from q,
 // staging them into B.
-template <int SCHEME>
+template <int SCHEME, bool FROM_LDS>
 __device__ __forceinline__ void rec_window(const Coef &k, const Stream &s, uint32_t pid,
-                                           Particle &q, int64_t base, int hi, Stage<SCHEME> &B)
+                                           Particle &q, int64_t base, int hi, Stage<SCHEME> &B,
+                                           const float *zl)
 {
     Noise4 z;
     float xb = q.xf + k.phi;
 #pragma unroll
     for (int t = 0; t < Stage<SCHEME>::B; ++t)
         if (t < hi)
-            rec_slot<SCHEME>(k, s, pid, q, xb, z, base, t, B);
+            rec_slot<SCHEME, FROM_LDS>(k, s, pid, q, xb, z, base, t, B, zl);
 }
 
 // One pipeline trip: reverse window m from R while recomputing window m-1 (from q) into W. The
 // sub-window holding the loss-window start (m == m_chk) runs the two halves one after the other.
-template <int SCHEME, int VFORM>
+template <int SCHEME, int VFORM, bool FROM_LDS>
 __device__ __forceinline__ void trip(const Coef &k, const RevCoef &rc, const Stream &s,
                                      uint32_t pid, Particle &q, int64_t m, int64_t m_chk,
                                      const RevCtx &cx, const Stage<SCHEME> &R, Stage<SCHEME> &W,
-                                     Rev &r)
+                                     const float *zl, Rev &r)
 {
     constexpr int kB = Stage<SCHEME>::B;
     if (m == m_chk) {
         rev_window<SCHEME, VFORM, true>(k, rc, R, m * kB, kB, cx, 0.0f, r);
-        rec_window<SCHEME>(k, s, pid, q, (m - 1) * kB, kB, W);
+        rec_window<SCHEME, FROM_LDS>(k, s, pid, q, (m - 1) * kB, kB, W, zl);
         return;
     }
     const float add_w = (VFORM && m * kB >= cx.wb) ? cx.invW : 0.0f;
@@ -403,7 +434,7 @@ __device__ __forceinline__ void trip(const Coef &k, const RevCoef &rc, const Str
     float xb = q.xf + k.phi;
 #pragma unroll
     for (int t = 0; t < kB; ++t) {
-        rec_slot<SCHEME>(k, s, pid, q, xb, z, (m - 1) * kB, t, W);
+        rec_slot<SCHEME, FROM_LDS>(k, s, pid, q, xb, z, (m - 1) * kB, t, W, zl);
         const int u = kB - 1 - t;
         rev_slot<SCHEME, VFORM, false>(k, rc, R, u, m * kB + u, cx, add_w, r);
     }
@@ -440,10 +471,11 @@ __device__ __forceinline__ void flush(Rev &r, double (&A64)[kSums])
 // reversed from one staging buffer, window m-1 is recomputed into the other, in the same
 // instruction stream, so the two dependency chains fill each other's latency (the adjoint runs
 // at one wavefront per SIMD for 2^16-particle ensembles).
-template <int SCHEME, int VFORM>
+template <int SCHEME, int VFORM, bool ZLDS>
 __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
 {
     constexpr int kStage = Stage<SCHEME>::B;
+    extern __shared__ float zbuf[];  // ZLDS: [waves per block][z_slots][64]
     Lane L;
     if (!locate(a, L))
         return;
@@ -484,9 +516,16 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
         // each earlier sub-window start; the last one's start state stays in registers
         Particle p[1] = {ck};
         int64_t step = s0;
+        float *zl = nullptr;  // the lane's LDS noise copy of sub-window m0 (ZLDS)
+        if constexpr (ZLDS)
+            zl = zbuf + (size_t)(threadIdx.x >> 6) * a.z_slots * 64 + L.lane;
         for (int64_t m = m0; m < m1; ++m) {
             put_state(sub + (size_t)(m - m0) * 7 * N, N, L.g, p[0]);
-            advance<SCHEME, 1, 1>(k, s, pid, p, step, (m + 1) * kStage);
+            if constexpr (ZLDS)
+                level1_window<SCHEME>(k, s, pid[0], p[0], m * kStage,
+                                      zl + (size_t)(m - m0) * kStage * 64);
+            else
+                advance<SCHEME, 1, 1>(k, s, pid, p, step, (m + 1) * kStage);
         }
         if (j > 0)
             ck = get_state(a.ckpt + (size_t)(j - 1) * 7 * N, N, L.g);
@@ -497,7 +536,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
         const int hi1 = (int)(s1 - m1 * kStage);
         if (hi1 < kStage) {
             // the run's final sub-window is shorter: recompute and reverse it on its own
-            rec_window<SCHEME>(k, s, pid[0], q, m1 * kStage, hi1, SA);
+            rec_window<SCHEME, false>(k, s, pid[0], q, m1 * kStage, hi1, SA, nullptr);
             rev_window<SCHEME, VFORM, true>(k, rc, SA, m1 * kStage, hi1, cx, 0.0f, r);
             flush(r, A64);
             if (m1 == m0)
@@ -506,7 +545,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             q = get_state(sub + (size_t)(m - m0) * 7 * N, N, L.g);
         }
         // prologue: stage window m into SA
-        rec_window<SCHEME>(k, s, pid[0], q, m * kStage, kStage, SA);
+        rec_window<SCHEME, false>(k, s, pid[0], q, m * kStage, kStage, SA, nullptr);
         Particle nxt;
         if (m > m0)
             nxt = get_state(sub + (size_t)(m - 1 - m0) * 7 * N, N, L.g);
@@ -520,7 +559,8 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             q = nxt;
             if (m - 1 > m0)
                 nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
-            trip<SCHEME, VFORM>(k, rc, s, pid[0], q, m, m_chk, cx, SA, SB, r);
+            trip<SCHEME, VFORM, ZLDS>(k, rc, s, pid[0], q, m, m_chk, cx, SA, SB,
+                                      zl + (size_t)(m - 1 - m0) * kStage * 64, r);
             flush(r, A64);
             --m;
             if (m == m0) {
@@ -531,7 +571,8 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             q = nxt;
             if (m - 1 > m0)
                 nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
-            trip<SCHEME, VFORM>(k, rc, s, pid[0], q, m, m_chk, cx, SB, SA, r);
+            trip<SCHEME, VFORM, ZLDS>(k, rc, s, pid[0], q, m, m_chk, cx, SB, SA,
+                                      zl + (size_t)(m - 1 - m0) * kStage * 64, r);
             flush(r, A64);
             --m;
         }
@@ -593,6 +634,20 @@ __global__ __launch_bounds__(64) void k_adj_finalize(AdjArgs a, int32_t phase)
 }  // namespace abp
 
 using namespace abp;
+
+// LDS one 256-thread block of the backward kernel may take for its noise copy: the smaller of the
+// per-block limit and the CU's LDS, so that a CU still holds its four wavefronts (one per SIMD).
+static size_t lds_per_block_limit()
+{
+    int dev = 0, per_block = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess)
+        return 0;
+    return (size_t)(per_block < per_cu ? per_block : per_cu);
+}
 
 extern "C" size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set, int64_t n_steps,
                                               int64_t ckpt_every)
@@ -679,16 +734,32 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
     const int64_t waves = (int64_t)n_sets * L.tiles;
     const unsigned grid = (unsigned)((waves * 64 + 255) / 256);
     const bool heun = cfg->scheme == ABP_HEUN;
-    if (phase == 0 && heun)
-        hipLaunchKernelGGL(k_adj_forward<1>, dim3(grid), dim3(256), 0, st, a);
-    else if (phase == 0)
-        hipLaunchKernelGGL(k_adj_forward<0>, dim3(grid), dim3(256), 0, st, a);
-    else if (heun)
-        hipLaunchKernelGGL((k_adj_backward<1, 0>), dim3(grid), dim3(256), 0, st, a);
-    else if (a.vform)
-        hipLaunchKernelGGL((k_adj_backward<0, 1>), dim3(grid), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_adj_backward<0, 0>), dim3(grid), dim3(256), 0, st, a);
+    if (phase == 0) {
+        if (heun)
+            hipLaunchKernelGGL(k_adj_forward<1>, dim3(grid), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_adj_forward<0>, dim3(grid), dim3(256), 0, st, a);
+    } else {
+        // level-1 noise in LDS when four wavefronts of it fit in one CU's LDS (and one block's
+        // share is allowed); else it is regenerated
+        const int B = heun ? Stage<1>::B : Stage<0>::B;
+        a.z_slots = (int32_t)(a.K - B);
+        const size_t z_bytes = sizeof(float) * 64 * (size_t)a.z_slots * 4;  // per 256-thread block
+        const bool zlds = a.z_slots > 0 && z_bytes <= lds_per_block_limit();
+        const size_t lds = zlds ? z_bytes : 0;
+        if (heun && zlds)
+            hipLaunchKernelGGL((k_adj_backward<1, 0, true>), dim3(grid), dim3(256), lds, st, a);
+        else if (heun)
+            hipLaunchKernelGGL((k_adj_backward<1, 0, false>), dim3(grid), dim3(256), 0, st, a);
+        else if (a.vform && zlds)
+            hipLaunchKernelGGL((k_adj_backward<0, 1, true>), dim3(grid), dim3(256), lds, st, a);
+        else if (a.vform)
+            hipLaunchKernelGGL((k_adj_backward<0, 1, false>), dim3(grid), dim3(256), 0, st, a);
+        else if (zlds)
+            hipLaunchKernelGGL((k_adj_backward<0, 0, true>), dim3(grid), dim3(256), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_adj_backward<0, 0, false>), dim3(grid), dim3(256), 0, st, a);
+    }
     if (hipGetLastError() != hipSuccess)
         return ABP_E_HIP;
     hipLaunchKernelGGL(k_adj_finalize, dim3((unsigned)n_sets), dim3(64), 0, st, a, phase);
