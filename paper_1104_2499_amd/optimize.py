@@ -53,7 +53,7 @@ def _robust_grad(rows, cfg, ws, loss, clip_q: float) -> torch.Tensor:
 
 
 def adam_ratchet(n_sets: int = 1024, n: int = 1024, steps: int = 50_000, window: int = 10_000,
-                 ckpt: int = 250, iters: int = 50, seed: int = 3, lr: float = 1e-2,
+                 ckpt: int = 160, iters: int = 50, seed: int = 3, lr: float = 1e-2,
                  lookback: int = 0, clip_q: float | None = None,
                  verbose: bool = False) -> AdamResult:
     """lookback > 0 uses the decayed adjoint estimator; clip_q winsorises per-particle gradients.
@@ -117,7 +117,7 @@ if __name__ == "__main__":
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--steps", type=int, default=50_000)
     ap.add_argument("--window", type=int, default=10_000)
-    ap.add_argument("--ckpt", type=int, default=250)
+    ap.add_argument("--ckpt", type=int, default=160)
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--lookback", type=int, default=0)
