@@ -198,8 +198,8 @@ int orc_integrate(const orc_params *p, int scheme, double dt, int64_t step0, int
 {
     if (!(dt > 0.0) || n_steps < 0 || step0 < 0 || n < 0 || p->D < 0.0)
         return -1;
-    if ((step0 + n_steps) / 4 > 0xFFFFFFFFll)
-        return -1;
+    if (n_steps > 0 && (step0 + n_steps - 1) / 4 > 0xFFFFFFFFll)
+        return -1; /* the last step's noise block must fit the 32-bit counter word */
     const double sig = sqrt(2.0 * p->D * dt);
 #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t i = 0; i < n; ++i) {

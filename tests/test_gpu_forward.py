@@ -333,3 +333,21 @@ def test_time_histogram_edges(gpu):
                       hist_acc=torch.zeros(12, dtype=torch.int64, device="cuda"))
     with pytest.raises(ValueError):
         api.integrate(st, 10, BASE, seed=3, hist_stride=5, hist_acc=None)
+
+
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_largest_step_index(gpu, orc, scheme):
+    """The last steps the ABI allows (step0 + n_steps = 2^34: the Philox block counter n/4 at its
+    top 32-bit values) against the oracle, starting mid-block; one step more is rejected."""
+    from paper_1104_2499_amd import api
+
+    n, top = 333, 1 << 34
+    s = api.init_state(n, 6, set_id=3)
+    api.integrate(s, 11, BASE, scheme=scheme, seed=6, set_id=3, step0=top - 11)
+    x0, v0, e0 = orc.init_state(n, 6, 3)
+    x, v, e, _, _ = orc.integrate(BASE, x0, v0, e0, 11, scheme=0 if scheme == "em" else 1,
+                                  seed=6, set_id=3, step0=top - 11)
+    err = mixed_err((_np(s.x64()), _np(s.v64()), _np(s.e64())), (x, v, e))
+    assert err.max() <= 1e-6
+    with pytest.raises(api.AbpError, match="ABP_E_ARG"):
+        api.integrate(s, 1, BASE, scheme=scheme, seed=6, step0=top)
