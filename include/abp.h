@@ -72,7 +72,8 @@ typedef struct abp_run {
      * after every absolute step index n with step0 < n <= step0 + n_steps and n a multiple of
      * hist_stride, each particle's x_n mod 1 is counted into d_hist_acc[hist_bins] (bins as for
      * the final-position histogram). Counts are added to what d_hist_acc holds, so chunked calls
-     * accumulate like one call; the caller zeroes it. hist_bins: power of two <= 4096. */
+     * accumulate like one call; the caller zeroes it. hist_bins: power of two <= 4096. One call
+ * takes at most 2^24 - 1 samples (n_steps / hist_stride < 2^24 - 1); chunk longer runs. */
     int64_t hist_stride;
     uint64_t *d_hist_acc;  /* device, 8-byte aligned */
     int32_t hist_bins;

@@ -1,5 +1,7 @@
 // api.hip -- library-wide entry points: version and status strings, the device check, the
 // initial condition and the raw Philox generator.
+#include <atomic>
+
 #include "common.hpp"
 #include "reduce.hpp"
 
@@ -7,18 +9,21 @@ namespace abp {
 
 abp_status check_device()
 {
-    static int cache[64];  // 0 = unknown, 1 = gfx950, 2 = other
+    static std::atomic<int> cache[64];  // 0 = unknown, 1 = gfx950, 2 = other (per device)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return ABP_E_DEVICE;
-    if (dev >= 0 && dev < 64 && cache[dev])
-        return cache[dev] == 1 ? ABP_OK : ABP_E_DEVICE;
+    if (dev >= 0 && dev < 64) {
+        const int known = cache[dev].load(std::memory_order_relaxed);
+        if (known)
+            return known == 1 ? ABP_OK : ABP_E_DEVICE;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
         return ABP_E_DEVICE;
     const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
     if (dev >= 0 && dev < 64)
-        cache[dev] = ok ? 1 : 2;
+        cache[dev].store(ok ? 1 : 2, std::memory_order_relaxed);
     return ok ? ABP_OK : ABP_E_DEVICE;
 }
 

@@ -267,6 +267,9 @@ extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const
     if (r->hist_stride > 0 && (r->hist_bins < 1 || !bins_ok(r->hist_bins) || !r->d_hist_acc ||
                                !aligned(r->d_hist_acc, 8)))
         return ABP_E_ARG;
+    // a block's LDS counts are 32-bit: at most 2^32 - 1 samples of its (<= 256) particles per call
+    if (r->hist_stride > 0 && (r->n_steps / r->hist_stride + 1) * 256 > (int64_t)0xFFFFFFFF)
+        return ABP_E_ARG;
     const int64_t end = r->step0 + r->n_steps;
     const bool snap_write = r->win_begin >= r->step0 && r->win_begin <= end;
     const bool reduce = d_ws != nullptr;

@@ -100,6 +100,7 @@ def test_integrate_rejects_bad_arguments_without_a_device(lib):
     for stride, ptr, bins_ in ((-1, 0x10000, 64), (10, 0x10000, 0), (10, 0x10000, 48),
                                (10, 0x10000, 8192), (10, 0, 64), (10, 0x10004, 64)):
         assert call(r=_lib.AbpRun(1e-3, 100, 0, -1, 42, 0, 0, stride, ptr, bins_)) == E_ARG
+    assert call(r=_lib.AbpRun(1e-3, 1 << 24, 0, -1, 42, 0, 0, 1, 0x10000, 64)) == E_ARG
     assert call(tune=_lib.AbpTuning(96, 1, 1, 0)) == E_ARG
     assert call(tune=_lib.AbpTuning(256, 3, 1, 0)) == E_ARG
     assert call(tune=_lib.AbpTuning(256, 1, 4, 0)) == E_ARG
