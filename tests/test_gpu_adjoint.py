@@ -249,3 +249,28 @@ def test_heun_rejects_lookback(gpu):
     cfg = adjoint.AdjointConfig(n=64, steps=100, window=10, ckpt=10, scheme="heun", lookback=50)
     with pytest.raises(api.AbpError, match="ABP_E_ARG"):
         adjoint.forward(adjoint.param_rows(_theta(1), cfg), cfg, adjoint.workspace(1, cfg))
+
+
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+@pytest.mark.parametrize("n,S,W,K", [(1, 1, 1, 1), (1, 5, 5, 3), (3, 17, 2, 1), (65, 40, 40, 40)])
+def test_degenerate_sizes(gpu, orc, scheme, n, S, W, K):
+    """Tiny ensembles and horizons (one particle, one step, windows covering the whole run, a
+    partial tile) against the FP64 adjoint: at these horizons FP32 and FP64 agree closely."""
+    from paper_1104_2499_amd import adjoint, api
+
+    theta = _theta(1, jitter=0.1, seed=2)
+    cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=K, seed=2, scheme=scheme)
+    rows = adjoint.param_rows(theta, cfg)
+    ws = adjoint.workspace(1, cfg)
+    loss = adjoint.forward(rows, cfg, ws)
+    g, gp = adjoint.backward(rows, cfg, ws, torch.ones(1, dtype=torch.float64), per_particle=True)
+    r = api.run(_params(theta[0]), n=n, steps=S, window=W, scheme=scheme, seed=2, bins=0)
+    assert float(loss[0].cpu()) == r.mean_v
+    x0, v0, e0 = orc.init_state(n, 2)
+    J, go = orc.adjoint(_params(theta[0]), x0, v0, e0, S, W, seed=2,
+                        scheme=orc.EM if scheme == "em" else orc.HEUN)
+    want = go.mean(axis=0)
+    np.testing.assert_allclose(g.cpu().numpy()[0], want, rtol=1e-4,
+                               atol=1e-5 * np.abs(want).max())
+    np.testing.assert_allclose(gp.cpu().numpy()[0], go, rtol=1e-3,
+                               atol=1e-5 * np.abs(go).max())
