@@ -152,17 +152,19 @@ def sweep_bench(reps: int = 2) -> dict:
             "finite_sets": int(np.isfinite(r.mean_v).sum())}
 
 
-def adjoint_bench(reps: int = 10, scheme: str = "em") -> dict:
+def adjoint_bench(reps: int = 10, scheme: str = "em", ckpt: int | None = None) -> dict:
     """Cost of the checkpointed adjoint (forward with checkpoints + backward) relative to the
     plain forward of the same ensemble and scheme: 65536 particles, 1e4 steps, W = 2000,
-    K = 100."""
+    checkpoints every K = 100 steps unless `ckpt` is given."""
+    import numpy as np
     import torch
 
     from paper_1104_2499_amd import adjoint, api
     from paper_1104_2499_amd.workloads import BASE_PARAMS, WORKLOADS
 
     wl = WORKLOADS["adjoint-64k"]
-    n, S, W, K = wl["n"], wl["steps"], wl["window"], wl["ckpt"]
+    n, S, W = wl["n"], wl["steps"], wl["window"]
+    K = wl["ckpt"] if ckpt is None else ckpt
     stream = torch.cuda.current_stream()
     cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=K, seed=wl["seed"], scheme=scheme)
     theta = torch.tensor([[BASE_PARAMS[k] for k in adjoint.GRAD_KEYS]], dtype=torch.float64)
@@ -189,12 +191,15 @@ def adjoint_bench(reps: int = 10, scheme: str = "em") -> dict:
         e1.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    t_plain = timed(plain)
-    t_fwd = timed(lambda: adjoint.forward(rows, cfg, ws))
-    t_bwd = timed(lambda: adjoint.backward(rows, cfg, ws, gloss))
+    # five interleaved trials of each; medians (the one-wavefront-per-SIMD plain forward varies by
+    # a few percent from run to run)
+    trials = [(timed(plain), timed(lambda: adjoint.forward(rows, cfg, ws)),
+               timed(lambda: adjoint.backward(rows, cfg, ws, gloss))) for _ in range(5)]
+    t_plain, t_fwd, t_bwd = (float(np.median([t[i] for t in trials])) for i in range(3))
     loss = float(adjoint.forward(rows, cfg, ws)[0].cpu())
     mean_v = float(plain()[0].cpu())
-    return {"workload": "adjoint-64k", "scheme": scheme, "plain_forward_ms": t_plain,
+    return {"workload": "adjoint-64k", "scheme": scheme, "ckpt": K,
+            "workspace_bytes": int(ws.numel()), "plain_forward_ms": t_plain,
             "adjoint_forward_ms": t_fwd,
             "adjoint_backward_ms": t_bwd, "cost_ratio": (t_fwd + t_bwd) / t_plain,
             "loss_equals_forward_mean": loss == mean_v,
@@ -217,11 +222,14 @@ def main() -> int:
     ap.add_argument("--tune", default=None, help="block,ppl,unroll (default: library default)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint cost measurements (EM and Heun), one JSON line each")
+    ap.add_argument("--adjoint-ckpt", type=int, nargs="*", default=None,
+                    help="checkpoint intervals for --adjoint-only (default: the workload's)")
     args = ap.parse_args()
 
     if args.adjoint_only:
-        for scheme in ("em", "heun"):
-            print(json.dumps(adjoint_bench(scheme=scheme)), flush=True)
+        for ckpt in args.adjoint_ckpt or [None]:
+            for scheme in ("em", "heun"):
+                print(json.dumps(adjoint_bench(scheme=scheme, ckpt=ckpt)), flush=True)
         return 0
 
     if args.copy_probe:
