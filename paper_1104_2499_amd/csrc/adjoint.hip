@@ -270,11 +270,14 @@ __device__ __forceinline__ void level1_window(const Coef &k, const Stream &s, ui
     }
 }
 
-// Adjoint state and the per-window FP32 sums the gradient is assembled from:
-//   A0 = sum lam_v dt cos th      A1 = sum lam_v dt cos 2th     A2 = sum lam_v sigma xi
+// Adjoint state and the per-window FP32 sums the gradient is assembled from (Euler-Maruyama;
+// Heun sums the same terms at both drift points with weights lam' and nu, and the factor dt/2 is
+// applied at the end):
+//   A0 = sum lam_v dt cos th      A1 = sum lam_v dt cos^2 th    A2 = sum lam_v sigma xi
 //   A3 = sum lam_v dt e v         A4 = sum lam_e dt e v^2       A5 = sum lam_e dt
 //   A6 = sum lam_e dt e           A7 = sum lam_v dt v           A8 = sum lam_v dt
-// (lam = lambda_{n+1}); the parameter constants are applied once at the end.
+// (lam = lambda_{n+1}); sum lam_v dt cos 2th = 2 A1 - A8 and the parameter constants are applied
+// once at the end.
 constexpr int kSums = 9;
 
 struct Rev {
@@ -300,11 +303,11 @@ __device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc, co
         r.lx -= cx.jscale;  // the window-start position enters J with weight -1/(W dt)
     const float c = B.c[t], sn = B.s[t], v = B.v[t], e = B.e[t];
     const float lvdt = r.lv * k.dt, ledt = r.le * k.dt;
-    const float c2 = fmaf(c + c, c, -1.0f);  // cos 2th
     const float ev = e * v;
     const float lev = ledt * ev;
-    r.A[0] = fmaf(lvdt, c, r.A[0]);
-    r.A[1] = fmaf(lvdt, c2, r.A[1]);
+    const float wc = lvdt * c;
+    r.A[0] += wc;
+    r.A[1] = fmaf(wc, c, r.A[1]);
     r.A[2] = fmaf(r.lv, B.z[t], r.A[2]);
     r.A[3] = fmaf(lvdt, ev, r.A[3]);
     r.A[4] = fmaf(lev, v, r.A[4]);
@@ -334,22 +337,24 @@ __device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc, co
 //   mu = J(yp)^T lam',  nu = lam' + dt mu,  lam_n = lam' + dt/2 (mu + J(y)^T nu);
 // the parameter terms are dt/2 f_theta(yp)^T lam' + dt/2 f_theta(y)^T nu, and sigma enters
 // through both the corrector and the predictor: (lam'_v + dt/2 mu_v) xi.
+// J(y)^T w at a drift point with cos c, sin sn, v, e and ev = e v.
 __device__ __forceinline__ void jac_t(const Coef &k, const RevCoef &rc, float c, float sn, float v,
-                                      float e, float wx, float wv, float we, float &ox, float &ov,
-                                      float &oe)
+                                      float e, float ev, float wx, float wv, float we, float &ox,
+                                      float &ov, float &oe)
 {
     const float upp = rc.m4pi2U0 * (sn * fmaf(rc.eight_a, c, 1.0f));  // U''(x)
     const float d2v = k.d2 * v;
     ox = -upp * wv;
-    ov = fmaf(-2.0f * d2v * e, we, fmaf(fmaf(k.d2, e, -k.g0), wv, wx));
+    ov = fmaf((-2.0f * k.d2) * we, ev, fmaf(fmaf(k.d2, e, -k.g0), wv, wx));
     oe = fmaf(d2v, wv, -fmaf(d2v, v, k.c) * we);
 }
 
-__device__ __forceinline__ void add_terms(Rev &r, float c, float v, float e, float wv, float we)
+__device__ __forceinline__ void add_terms(Rev &r, float c, float v, float e, float ev, float wv,
+                                          float we)
 {
-    const float ev = e * v;
-    r.A[0] = fmaf(wv, c, r.A[0]);
-    r.A[1] = fmaf(wv, fmaf(c + c, c, -1.0f), r.A[1]);
+    const float wc = wv * c;
+    r.A[0] += wc;
+    r.A[1] = fmaf(wc, c, r.A[1]);
     r.A[3] = fmaf(wv, ev, r.A[3]);
     r.A[4] = fmaf(we * ev, v, r.A[4]);
     r.A[5] += we;
@@ -365,13 +370,14 @@ __device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc, 
     if (CHECK && n + 1 == cx.wb)
         r.lx -= cx.jscale;
     const float h = k.half_dt;
+    const float evt = B.et[t] * B.vt[t], ev = B.e[t] * B.v[t];
     float mx, mv, me;
-    jac_t(k, rc, B.ct[t], B.st[t], B.vt[t], B.et[t], r.lx, r.lv, r.le, mx, mv, me);
+    jac_t(k, rc, B.ct[t], B.st[t], B.vt[t], B.et[t], evt, r.lx, r.lv, r.le, mx, mv, me);
     const float nx = fmaf(k.dt, mx, r.lx), nv = fmaf(k.dt, mv, r.lv), ne = fmaf(k.dt, me, r.le);
     float px, pv, pe;
-    jac_t(k, rc, B.c[t], B.s[t], B.v[t], B.e[t], nx, nv, ne, px, pv, pe);
-    add_terms(r, B.ct[t], B.vt[t], B.et[t], h * r.lv, h * r.le);
-    add_terms(r, B.c[t], B.v[t], B.e[t], h * nv, h * ne);
+    jac_t(k, rc, B.c[t], B.s[t], B.v[t], B.e[t], ev, nx, nv, ne, px, pv, pe);
+    add_terms(r, B.ct[t], B.vt[t], B.et[t], evt, r.lv, r.le);  // times dt/2 at the end
+    add_terms(r, B.c[t], B.v[t], B.e[t], ev, nv, ne);
     r.A[2] = fmaf(fmaf(h, mv, r.lv), B.z[t], r.A[2]);
     r.lx = fmaf(h, mx + px, r.lx);
     r.lv = fmaf(h, mv + pv, r.lv);
@@ -577,11 +583,19 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             --m;
         }
     }
-    // dJ/d(U0, a, D, d2, q, c, gamma0, F0) from the sums (FP64)
+    // dJ/d(U0, a, D, d2, q, c, gamma0, F0) from the sums (FP64); the Heun sums other than A2
+    // carry their factor dt/2 here
     const double two_pi = 2.0 * 3.14159265358979323846;
+    if constexpr (SCHEME == 1) {
+#pragma unroll
+        for (int i = 0; i < kSums; ++i)
+            if (i != 2)
+                A64[i] *= (double)k.half_dt;
+    }
+    const double cos2 = 2.0 * A64[1] - A64[8];  // sum of lam_v dt cos 2th
     double g[kGrad];
-    g[0] = -two_pi * (A64[0] + (double)rc.a2 * A64[1]);
-    g[1] = -(double)rc.four_pi_U0 * A64[1];
+    g[0] = -two_pi * (A64[0] + (double)rc.a2 * cos2);
+    g[1] = -(double)rc.four_pi_U0 * cos2;
     g[2] = (double)rc.inv2D * A64[2];
     g[3] = A64[3] - A64[4];
     g[4] = A64[5];
