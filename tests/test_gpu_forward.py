@@ -376,3 +376,30 @@ def test_benchmark_configuration_full_size(gpu, orc):
     mean, se, _ = orc.reduce(xs, x, W * wl["dt"], wl["bins"])
     print(f"gpu {a.mean_v:.6e} +- {a.stderr:.2e}; oracle subset {mean:.6e} +- {se:.2e}")
     assert abs(a.mean_v - mean) <= 4 * np.hypot(a.stderr, se)
+
+
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_sharding_by_particle_ids(gpu, scheme):
+    """What a multi-GPU run would do, on one GPU: two shards holding particle ids [0, n_a) and
+    [n_a, n) (abp_state.id0) give, bit for bit, the states of the unsharded run; their histograms
+    add up to its histogram and their tile sums to its mean velocity."""
+    from paper_1104_2499_amd import api
+
+    n, n_a, S, W, bins = 5000, 2048, 3001, 1000, 64
+    full = api.run(BASE, n=n, steps=S, window=W, scheme=scheme, seed=13, bins=bins)
+    parts = []
+    for id0, m in ((0, n_a), (n_a, n - n_a)):
+        st = api.init_state(m, 13, id0=id0)
+        snap = api.State.empty(m, id0=id0)
+        ws = api.reduce_workspace(m, bins)
+        api.integrate(st, S, BASE, scheme=scheme, seed=13, win_begin=S - W, snap=snap, ws=ws,
+                      n_bins=bins)
+        out, hist = api.reduce(ws, m, bins, W * 1e-3)
+        parts.append((st, _np(out), _np(hist), m))
+    for name in ("cell", "xf", "v", "e"):
+        joined = torch.cat([getattr(p[0], name) for p in parts])
+        assert torch.equal(joined, getattr(full.state, name)), name
+    assert torch.equal(torch.cat([p[0].lo for p in parts], dim=1), full.state.lo)
+    np.testing.assert_array_equal(parts[0][2] + parts[1][2], _np(full.hist))
+    combined = sum(p[1][0] * p[3] for p in parts) / n
+    assert abs(combined - full.mean_v) <= 1e-14 * max(1.0, abs(full.mean_v))
