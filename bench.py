@@ -106,9 +106,10 @@ def cpu_baseline(wl: dict, params: dict, seconds_budget: float = 15.0) -> dict:
                       f"{dt_s:.1f} s"}
 
 
-def sweep_bench(reps: int = 2) -> dict:
+def sweep_bench(reps: int = 2, tune_batched=None, tune_single=None) -> dict:
     """The 4096-set ratchet sweep in one persistent launch, and the single-set throughput of the
-    same scheme (2^20 particles of the base parameters) for comparison."""
+    same scheme (2^20 particles of the base parameters) for comparison; each with its launch
+    shape (None = library default)."""
     import numpy as np
     import torch
 
@@ -119,12 +120,13 @@ def sweep_bench(reps: int = 2) -> dict:
     table, n_traj, n_steps = sweep_table(wl["n_sets"], seed=wl["seed"])
     work = float((n_traj.astype(np.int64) * n_steps).sum())
     ws = api.batched_workspace(n_traj, wl["bins"])
-    api.sweep(table, n_traj, n_steps, scheme=wl["scheme"], seed=wl["seed"], bins=wl["bins"], ws=ws)
+    api.sweep(table, n_traj, n_steps, scheme=wl["scheme"], seed=wl["seed"], bins=wl["bins"], ws=ws,
+              tune=tune_batched)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         r = api.sweep(table, n_traj, n_steps, scheme=wl["scheme"], seed=wl["seed"],
-                      bins=wl["bins"], ws=ws)
+                      bins=wl["bins"], ws=ws, tune=tune_batched)
     torch.cuda.synchronize()
     t_sweep = (time.perf_counter() - t0) / reps
 
@@ -135,7 +137,7 @@ def sweep_bench(reps: int = 2) -> dict:
     def single():
         api.reset_state(state, wl["seed"])
         api.integrate(state, S, BASE_PARAMS, wl["dt"], wl["scheme"], wl["seed"], 0, 0, S // 2, snap,
-                      rws, wl["bins"])
+                      rws, wl["bins"], tune_single)
         api.reduce(rws, n, wl["bins"], S // 2 * wl["dt"])
     single()
     torch.cuda.synchronize()
@@ -219,7 +221,9 @@ def main() -> int:
     ap.add_argument("--no-sweep", action="store_true", help="skip the 4096-set sweep line item")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device copy (reference for HBM counters)")
-    ap.add_argument("--tune", default=None, help="block,ppl,unroll (default: library default)")
+    ap.add_argument("--tune", default="auto",
+                    help='launch shapes: "auto" (the autotuner\'s, tuned once per device and '
+                         'cached), "default" (the library\'s) or block,ppl,unroll')
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint cost measurements (EM and Heun), one JSON line each")
     ap.add_argument("--adjoint-ckpt", type=int, nargs="*", default=None,
@@ -261,8 +265,15 @@ def main() -> int:
         wl["steps"] = args.sim_steps
         wl["window"] = args.sim_steps // 2
     n, S, W, bins, dt, seed = wl["n"], wl["steps"], wl["window"], wl["bins"], wl["dt"], wl["seed"]
-    tune = None
-    if args.tune:
+    tune = tune_batched = tune_em = None
+    if args.tune == "auto":
+        from paper_1104_2499_amd import tune as autotune
+
+        tune = autotune.tune("forward", wl["scheme"])
+        if not args.no_sweep:
+            tune_batched = autotune.tune("batched", WORKLOADS["sweep-4096"]["scheme"])
+            tune_em = autotune.tune("forward", WORKLOADS["sweep-4096"]["scheme"])
+    elif args.tune != "default":
         b, p, u = (int(t) for t in args.tune.split(","))
         tune = dict(block=b, ppl=p, unroll=u)
     dev = torch.device("cuda:0")
@@ -340,7 +351,9 @@ def main() -> int:
                    "hist_total": int(hist.sum().item())},
     }
     if not args.no_sweep:
-        line["sweep"] = sweep_bench()
+        line["sweep"] = sweep_bench(tune_batched=tune_batched, tune_single=tune_em)
+        line["sweep"]["tuning"] = {"batched": tune_batched or "default",
+                                   "single_set": tune_em or "default"}
         line["adjoint"] = adjoint_bench()
         line["adjoint_heun"] = adjoint_bench(scheme="heun")
     if not args.no_cpu_baseline:

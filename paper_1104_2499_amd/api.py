@@ -56,7 +56,17 @@ def make_params(params: dict | None = None) -> _lib.AbpParams:
     return _lib.AbpParams(*[float(d[k]) for k in PARAM_KEYS])
 
 
-def make_tuning(tune) -> _lib.AbpTuning | None:
+def make_tuning(tune, kind: str = "forward", scheme="em") -> _lib.AbpTuning | None:
+    """ABI tuning from None (library default), a dict of launch-shape fields, or "auto" (the
+    shape the autotuner cached for this device, kernel kind and scheme; default if none)."""
+    if isinstance(tune, str):
+        if tune != "auto":
+            raise ValueError('tune must be None, a dict of launch-shape fields, or "auto"')
+        from . import tune as _tune
+
+        name = scheme.lower() if isinstance(scheme, str) else (
+            "em" if scheme == _lib.ABP_EM else "heun")
+        tune = _tune.lookup(kind, name)
     if tune is None:
         return None
     if isinstance(tune, _lib.AbpTuning):
@@ -164,7 +174,7 @@ def integrate(state: State, n_steps: int, params: dict | None = None, dt: float 
         r.hist_stride, r.d_hist_acc, r.hist_bins = hist_stride, hist_acc.data_ptr(), hist_acc.numel()
     s = state.abi()
     sn = snap.abi() if snap is not None else None
-    t = make_tuning(tune)
+    t = make_tuning(tune, "forward", scheme)
     check(_lib.load().abp_integrate(ctypes.byref(p), ctypes.byref(r), ctypes.byref(s),
                                     ctypes.byref(sn) if sn is not None else None, _ptr(ws),
                                     0 if ws is None else ws.numel(), n_bins,
@@ -263,7 +273,7 @@ def sweep(table, n_traj, n_steps, window=None, dt: float = 1e-3, scheme="em", se
     out = torch.empty((n_sets, 2), dtype=torch.float64, device=device)
     hist = torch.empty((n_sets, max(bins, 1)), dtype=torch.int64, device=device)
     cfg = _lib.AbpBatch(dt, seed, scheme_id(scheme), bins)
-    tn = make_tuning(tune)
+    tn = make_tuning(tune, "batched", scheme)
     check(_lib.load().abp_integrate_batched(
         n_sets, t.ctypes.data, nt.ctypes.data, ns.ctypes.data,
         None if win is None else win.ctypes.data, ctypes.byref(cfg),

@@ -46,13 +46,18 @@ def _load_cache() -> dict:
         return {}
 
 
-def _store_cache(cache: dict) -> None:
+def _store_cache(cache: dict) -> bool:
+    """Write the cache; False (and nothing cached) if its location is not writable."""
     path = cache_path()
-    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
-    tmp = path + ".tmp"
-    with open(tmp, "w") as f:
-        json.dump(cache, f, indent=1, sort_keys=True)
-    os.replace(tmp, path)
+    try:
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        return False
+    return True
 
 
 def candidates(kind: str):
@@ -103,13 +108,15 @@ def _batched_probe(scheme: str, n_sets: int = 512, step_scale: float = 0.05):
 
 
 def tune(kind: str = "forward", scheme: str = "heun", force: bool = False,
-         verbose: bool = False) -> dict:
-    """Best launch shape for `kind` ("forward" or "batched") and `scheme`; cached."""
+         verbose: bool = False, probe: dict | None = None) -> dict:
+    """Best launch shape for `kind` ("forward" or "batched") and `scheme`; cached. `probe`
+    overrides the probe workload's sizes (forward: n, steps; batched: n_sets, step_scale)."""
     key = device_key(kind, scheme)
     cache = _load_cache()
     if not force and key in cache:
         return cache[key]["tune"]
-    make, work = (_forward_probe if kind == "forward" else _batched_probe)(scheme)
+    make, work = (_forward_probe if kind == "forward" else _batched_probe)(scheme,
+                                                                           **(probe or {}))
     results = []
     for cand in candidates(kind):
         ms = _time(make(cand))

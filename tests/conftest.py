@@ -22,6 +22,19 @@ def orc():
 
 
 @pytest.fixture(scope="session")
+def lib():
+    """The HIP library (built here if missing); its entry points validate arguments without a
+    device."""
+    import os
+
+    from paper_1104_2499_amd import _lib, build
+
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    return _lib.load()
+
+
+@pytest.fixture(scope="session")
 def gpu():
     """The HIP library on cuda:0. GPU tests fail (never skip) if the device or library is absent."""
     import torch

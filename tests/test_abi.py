@@ -16,15 +16,6 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(abp_[a-z0-9_]+)\s*\(", text)))
 
 
-@pytest.fixture(scope="module")
-def lib():
-    from paper_1104_2499_amd import _lib, build
-
-    if not os.path.exists(_lib.LIB_PATH):
-        build.build()
-    return _lib.load()
-
-
 def test_every_declared_symbol_is_exported_and_bound(lib):
     from paper_1104_2499_amd import _lib
 

@@ -108,3 +108,25 @@ def test_batched_rejects_bad_arguments(gpu):
     ws = torch.empty(64, dtype=torch.uint8, device="cuda")
     with pytest.raises(api.AbpError, match="ABP_E_WORKSPACE"):
         api.sweep(table, n_traj, n_steps, window, bins=32, ws=ws)
+
+
+def test_autotuner_picks_a_shape_that_changes_no_bits(gpu, tmp_path, monkeypatch):
+    """The autotuner times every candidate launch shape on a small probe, caches the fastest per
+    device, kernel and scheme, and api calls with tune="auto" use it; the results equal the
+    default shape's bit for bit."""
+    from paper_1104_2499_amd import api, tune
+
+    monkeypatch.setenv("ABP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    best_f = tune.tune("forward", "em", force=True, probe=dict(n=65536, steps=400))
+    best_b = tune.tune("batched", "em", force=True, probe=dict(n_sets=64, step_scale=0.01))
+    assert best_f in list(tune.candidates("forward"))
+    assert best_b in list(tune.candidates("batched"))
+    assert tune.lookup("forward", "em") == best_f and tune.lookup("batched", "em") == best_b
+    a = api.run(None, n=3000, steps=1001, scheme="em", seed=3, bins=64, tune="auto")
+    b = api.run(None, n=3000, steps=1001, scheme="em", seed=3, bins=64)
+    assert a.mean_v == b.mean_v and a.stderr == b.stderr and torch.equal(a.hist, b.hist)
+    table, n_traj, n_steps, window, _ = _small_sweep()
+    s1 = api.sweep(table, n_traj, n_steps, window, scheme="em", bins=16, tune="auto")
+    s2 = api.sweep(table, n_traj, n_steps, window, scheme="em", bins=16)
+    np.testing.assert_array_equal(s1.mean_v, s2.mean_v)
+    assert torch.equal(s1.hist, s2.hist)

@@ -46,3 +46,47 @@ def test_initial_theta_follows_sweep_table():
     table, _, _ = sweep_table(16, seed=3)
     for j, key in enumerate(GRAD_KEYS):
         np.testing.assert_array_equal(th[:, j], table[:, PARAM_KEYS.index(key)])
+
+
+def test_tuner_candidates_are_valid_launch_shapes(lib):
+    """Every shape the autotuner may pick passes the library's validation (on a host without a
+    gfx950 device the call then stops at the device check, not at the arguments)."""
+    import ctypes
+
+    from paper_1104_2499_amd import _lib, tune
+    from paper_1104_2499_amd.api import make_params, make_tuning
+
+    ptr = 0x10000
+    s = _lib.AbpState(ptr, ptr, ptr, ptr, ptr, 64, 0, 0)
+    r = _lib.AbpRun(1e-3, 100, 0, -1, 42, 0, 0)
+    p = make_params()
+    shapes = list(tune.candidates("forward")) + list(tune.candidates("batched"))
+    assert len(shapes) == 12 + 24
+    for shape in shapes:
+        t = make_tuning(shape)
+        rc = lib.abp_integrate(ctypes.byref(p), ctypes.byref(r), ctypes.byref(s), None, None, 0, 0,
+                               ctypes.byref(t), None)
+        assert rc != _lib.ABP_E_ARG, shape
+
+
+def test_tuner_cache_roundtrip(tmp_path, monkeypatch):
+    from paper_1104_2499_amd import _lib, tune
+    from paper_1104_2499_amd.api import make_tuning
+
+    monkeypatch.setenv("ABP_TUNE_CACHE", str(tmp_path / "sub" / "tune.json"))
+    monkeypatch.setattr(tune, "device_key", lambda kind, scheme: f"gfx950:256:{kind}:{scheme}")
+    assert tune.lookup("batched", "em") is None
+    assert make_tuning("auto", "batched", "em") is None
+    shape = dict(block=128, ppl=2, unroll=1, waves_per_simd=4)
+    assert tune._store_cache({"gfx950:256:batched:em": {"tune": shape}})
+    assert tune.lookup("batched", "em") == shape
+    t = make_tuning("auto", "batched", _lib.ABP_EM)
+    assert (t.block, t.ppl, t.unroll, t.waves_per_simd) == (128, 2, 1, 4)
+    assert make_tuning("auto", "forward", "heun") is None
+    with pytest.raises(ValueError):
+        make_tuning("fastest")
+    # an unwritable cache location is not an error: nothing is cached
+    blocker = tmp_path / "file"
+    blocker.write_text("x")
+    monkeypatch.setenv("ABP_TUNE_CACHE", str(blocker / "tune.json"))
+    assert tune._store_cache({"k": {}}) is False
