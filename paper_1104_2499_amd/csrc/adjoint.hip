@@ -40,12 +40,15 @@ struct RevCoef {
     float eight_a;     // 8a                  (U'' = -4 pi^2 U0 sin th (1 + 8a cos th))
     float m4pi2U0;     // -4 pi^2 U0
     float inv2D;       // 1 / (2D)            (d(sigma xi)/dD = sigma xi / (2D))
+    // the Euler-Maruyama reverse step runs on Lam = dt lam, with the step's dt folded in here
+    float m4pi2U0_dt;  // -4 pi^2 U0 dt
+    float d2_dt, g0_dt, c_dt, m2d2_dt;  // d2 dt, gamma0 dt, c dt, -2 d2 dt
 };
 
 struct AdjRow {
     Coef k;
     RevCoef r;
-    uint32_t pad[3];
+    uint32_t pad[2];  // 96 bytes
 };
 
 struct AdjArgs {
@@ -294,6 +297,8 @@ struct RevCtx {
     float jscale, invW, rho;
 };
 
+// Euler-Maruyama reverse step on Lam = dt lam (the loss-side constants in cx are scaled alike),
+// lam_n = lam' + dt J(y)^T lam'.
 template <int VFORM, bool CHECK>
 __device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc, const Stage<0> &B,
                                             int t, int64_t n, const RevCtx &cx, float add_w,
@@ -302,25 +307,24 @@ __device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc, co
     if (CHECK && !VFORM && n + 1 == cx.wb)
         r.lx -= cx.jscale;  // the window-start position enters J with weight -1/(W dt)
     const float c = B.c[t], sn = B.s[t], v = B.v[t], e = B.e[t];
-    const float lvdt = r.lv * k.dt, ledt = r.le * k.dt;
     const float ev = e * v;
-    const float lev = ledt * ev;
-    const float wc = lvdt * c;
+    const float lev = r.le * ev;
+    const float wc = r.lv * c;
     r.A[0] += wc;
     r.A[1] = fmaf(wc, c, r.A[1]);
     r.A[2] = fmaf(r.lv, B.z[t], r.A[2]);
-    r.A[3] = fmaf(lvdt, ev, r.A[3]);
+    r.A[3] = fmaf(r.lv, ev, r.A[3]);
     r.A[4] = fmaf(lev, v, r.A[4]);
-    r.A[5] += ledt;
-    r.A[6] = fmaf(ledt, e, r.A[6]);
-    r.A[7] = fmaf(lvdt, v, r.A[7]);
-    r.A[8] += lvdt;
+    r.A[5] += r.le;
+    r.A[6] = fmaf(r.le, e, r.A[6]);
+    r.A[7] = fmaf(r.lv, v, r.A[7]);
+    r.A[8] += r.lv;
     // transpose of the step Jacobian; U'' = -4 pi^2 U0 sin th (1 + 8a cos th)
-    const float nlx = fmaf(-lvdt, rc.m4pi2U0 * (sn * fmaf(rc.eight_a, c, 1.0f)), r.lx);
+    const float nlx = fmaf(-r.lv, rc.m4pi2U0_dt * (sn * fmaf(rc.eight_a, c, 1.0f)), r.lx);
     const float nlv =
-        fmaf(-2.0f * k.d2, lev, fmaf(r.lx, k.dt, fmaf(lvdt, fmaf(k.d2, e, -k.g0), r.lv)));
-    const float d2v = k.d2 * v;
-    const float nle = fmaf(lvdt, d2v, fmaf(-ledt, fmaf(d2v, v, k.c), r.le));
+        fmaf(rc.m2d2_dt, lev, fmaf(r.lx, k.dt, fmaf(r.lv, fmaf(rc.d2_dt, e, -rc.g0_dt), r.lv)));
+    const float d2v = rc.d2_dt * v;
+    const float nle = fmaf(r.lv, d2v, fmaf(-r.le, fmaf(d2v, v, rc.c_dt), r.le));
     if (VFORM) {
         r.lx = cx.rho * nlx;
         r.lv = fmaf(cx.rho, nlv, CHECK ? (n >= cx.wb ? cx.invW : 0.0f) : add_w);
@@ -493,8 +497,10 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
     const int64_t wb = a.S - a.W;
     RevCtx cx;
     cx.wb = wb;
-    cx.jscale = (float)(1.0 / ((double)a.W * a.dt));
-    cx.invW = (float)(1.0 / (double)a.W);
+    // Euler-Maruyama runs the reverse sweep on Lam = dt lam: its loss-side constants carry dt
+    const double lam_scale = SCHEME == 0 ? a.dt : 1.0;
+    cx.jscale = (float)(lam_scale / ((double)a.W * a.dt));
+    cx.invW = (float)(lam_scale / (double)a.W);
     cx.rho = a.rho;
     const int64_t m_chk = wb >= 1 ? (wb - 1) / kStage : -1;  // sub-window holding step wb - 1
     // exact form: J = (x_S - x_{S-W}) / (W dt); decayed form: J = (1/W) sum_{n >= S-W} v_n, which
@@ -591,6 +597,8 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
         for (int i = 0; i < kSums; ++i)
             if (i != 2)
                 A64[i] *= (double)k.half_dt;
+    } else {
+        A64[2] /= a.dt;  // sum of Lam_v sigma xi = dt sum lam_v sigma xi
     }
     const double cos2 = 2.0 * A64[1] - A64[8];  // sum of lam_v dt cos 2th
     double g[kGrad];
@@ -714,6 +722,11 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         r.r.eight_a = (float)(8.0 * p.a);
         r.r.m4pi2U0 = (float)(-4.0 * kPi * kPi * p.U0);
         r.r.inv2D = (float)(1.0 / (2.0 * p.D));
+        r.r.m4pi2U0_dt = (float)(-4.0 * kPi * kPi * p.U0 * cfg->dt);
+        r.r.d2_dt = (float)(p.d2 * cfg->dt);
+        r.r.g0_dt = (float)(p.gamma0 * cfg->dt);
+        r.r.c_dt = (float)(p.c * cfg->dt);
+        r.r.m2d2_dt = (float)(-2.0 * p.d2 * cfg->dt);
     }
     hipStream_t st = as_stream(stream);
     char *ws = reinterpret_cast<char *>(d_ws);
