@@ -208,6 +208,45 @@ def adjoint_bench(reps: int = 10, scheme: str = "em", ckpt: int | None = None) -
             "particle_steps": n * S}
 
 
+def adjoint_batched_bench(stage: int, ckpt: int, reps: int = 3) -> dict:
+    """One iteration of the batched-adjoint workload (1024 sets x 1024 particles x 5e4 EM steps,
+    W = 1e4): forward with checkpoints and backward, for a register staging length and a
+    checkpoint interval; medians of `reps` timed iterations after one warm-up."""
+    import numpy as np
+    import torch
+
+    from paper_1104_2499_amd import adjoint
+    from paper_1104_2499_amd.optimize import initial_theta
+    from paper_1104_2499_amd.workloads import WORKLOADS
+
+    wl = WORKLOADS["adjoint-batched-1k"]
+    theta = torch.tensor(initial_theta(wl["n_sets"], wl["seed"]))
+    cfg = adjoint.AdjointConfig(n=wl["n"], steps=wl["steps"], window=wl["window"], ckpt=ckpt,
+                                seed=wl["seed"], stage=stage)
+    rows = adjoint.param_rows(theta, cfg)
+    ws = adjoint.workspace(wl["n_sets"], cfg)
+    gloss = torch.ones(wl["n_sets"], dtype=torch.float64, device="cuda")
+    adjoint.forward(rows, cfg, ws)
+    adjoint.backward(rows, cfg, ws, gloss)
+    times = []
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        adjoint.forward(rows, cfg, ws)
+        ev[1].record()
+        adjoint.backward(rows, cfg, ws, gloss)
+        ev[2].record()
+        ev[2].synchronize()
+        times.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
+    nbytes = int(ws.numel())
+    del ws
+    torch.cuda.empty_cache()
+    return {"workload": "adjoint-batched-1k", "stage": stage, "ckpt": ckpt,
+            "workspace_bytes": nbytes,
+            "forward_ms": float(np.median([t[0] for t in times])),
+            "backward_ms": float(np.median([t[1] for t in times]))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,7 +267,14 @@ def main() -> int:
                     help="only the adjoint cost measurements (EM and Heun), one JSON line each")
     ap.add_argument("--adjoint-ckpt", type=int, nargs="*", default=None,
                     help="checkpoint intervals for --adjoint-only (default: the workload's)")
+    ap.add_argument("--adjoint-batched", action="store_true",
+                    help="only one batched-adjoint iteration per (staging, K) variant")
     args = ap.parse_args()
+
+    if args.adjoint_batched:
+        for stage, ckpt in ((16, 160), (8, 80), (8, 160), (16, 80)):
+            print(json.dumps(adjoint_batched_bench(stage, ckpt)), flush=True)
+        return 0
 
     if args.adjoint_only:
         for ckpt in args.adjoint_ckpt or [None]:

@@ -189,15 +189,18 @@ typedef struct abp_adjoint_cfg {
     int64_t n_steps;     /* S >= 1 */
     int64_t window;      /* W, 1 <= W <= S: the loss averages over the last W steps */
     int64_t ckpt_every;  /* K >= 1: forward checkpoint interval (e.g. about sqrt(S)); rounded up
-                            to a multiple of 16 (the backward pass stages 16 Euler-Maruyama or 8
-                            Heun steps at a time in registers). The gradient does not depend on K
-                            (bit for bit) */
+                            to a multiple of 16 (see stage_steps). The gradient does not depend on
+                            K (bit for bit) */
     uint64_t seed;       /* Philox key; set k uses counter word 2 = k */
     int64_t lookback;    /* 0: exact pathwise gradient. T > 0 (Euler-Maruyama only): each window
                             velocity's sensitivity is damped by (1 - 1/T) per step of look-back (a
                             biased, bounded-variance estimator for long chaotic horizons) */
     int32_t scheme;      /* ABP_EM or ABP_HEUN: the map whose discrete adjoint is taken */
-    int32_t pad;
+    int32_t stage_steps; /* steps the backward pass stages in registers at a time: 0 = default
+                            (16 for Euler-Maruyama, 8 for Heun); 8 lets two wavefronts share a
+                            SIMD (faster for ensembles of more than ~2 wavefronts per SIMD);
+                            16 is Euler-Maruyama only. Changes the grouping of the FP32 gradient
+                            sums, not the recursion */
 } abp_adjoint_cfg;
 
 /* Bytes of workspace: checkpoints (28 bytes per particle per segment), sub-checkpoints, and the

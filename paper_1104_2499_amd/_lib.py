@@ -50,7 +50,7 @@ class AbpAdjointCfg(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("n_steps", ctypes.c_int64), ("window", ctypes.c_int64),
                 ("ckpt_every", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("lookback", ctypes.c_int64), ("scheme", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("stage_steps", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER

@@ -32,13 +32,14 @@ class AdjointConfig:
     seed: int = 42
     lookback: int = 0         # 0 = exact gradient; T > 0 = sensitivities damped by (1 - 1/T)/step
     scheme: str = "em"        # "em" or "heun" (lookback > 0 needs "em")
+    stage: int = 0            # backward register staging: 0 = default, 8 = two wavefronts/SIMD
     fixed: dict = field(default_factory=lambda: {"phi": BASE_PARAMS["phi"]})
 
     def abi(self) -> _lib.AbpAdjointCfg:
         if self.scheme not in SCHEMES:
             raise ValueError(f"scheme must be one of {sorted(SCHEMES)}")
         return _lib.AbpAdjointCfg(self.dt, self.steps, self.window, self.ckpt, self.seed,
-                                  self.lookback, SCHEMES[self.scheme], 0)
+                                  self.lookback, SCHEMES[self.scheme], self.stage)
 
 
 def param_rows(theta: torch.Tensor, cfg: AdjointConfig) -> np.ndarray:

@@ -198,17 +198,19 @@ __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
 // Values of one sub-window staged for the reverse sweep, per step: cos and sin of the phase
 // 2 pi (x + phi), v and e (the rounded sums the drift saw), sigma xi; for Heun also the same at
 // the predictor point.
-template <int SCHEME>
+// NB = steps per sub-window: 16 or 8 for Euler-Maruyama (8 stages half the registers, so that
+// two wavefronts fit one SIMD), 8 for Heun.
+template <int SCHEME, int NB>
 struct Stage;
 
-template <>
-struct Stage<0> {
-    static constexpr int B = 16;
+template <int NB>
+struct Stage<0, NB> {
+    static constexpr int B = NB;
     float c[B], s[B], v[B], e[B], z[B];
 };
 
 template <>
-struct Stage<1> {
+struct Stage<1, 8> {
     static constexpr int B = 8;
     float c[B], s[B], v[B], e[B], ct[B], st[B], vt[B], et[B], z[B];
 };
@@ -216,10 +218,10 @@ struct Stage<1> {
 // Recompute slot t of a sub-window (absolute step base + t), staging its inputs. The noise is
 // regenerated or (FROM_LDS) read from the lane's LDS copy zl[64 t] kept by level 1. The staged
 // predictor repeats step_heun's own expressions, so it holds the values that step saw.
-template <int SCHEME, bool FROM_LDS>
+template <int SCHEME, bool FROM_LDS, class ST>
 __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_t pid, Particle &q,
-                                         float &xb, Noise4 &z, int64_t base, int t,
-                                         Stage<SCHEME> &B, const float *zl)
+                                         float &xb, Noise4 &z, int64_t base, int t, ST &B,
+                                         const float *zl)
 {
     float zs;
     if constexpr (FROM_LDS) {
@@ -255,11 +257,11 @@ __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_
 
 // Level 1 over one whole sub-window starting at absolute step base: the same arithmetic as
 // advance(), keeping each sigma*xi in the lane's LDS copy zw[64 t].
-template <int SCHEME>
+template <int SCHEME, int NB>
 __device__ __forceinline__ void level1_window(const Coef &k, const Stream &s, uint32_t pid,
                                               Particle &p, int64_t base, float *zw)
 {
-    constexpr int kB = Stage<SCHEME>::B;
+    constexpr int kB = NB;
 #pragma unroll
     for (int b = 0; b < kB / 4; ++b) {
         const Noise4 z = noise_block((uint32_t)((base >> 2) + b), pid, s.set, s.k0, s.k1, k.bm);
@@ -299,10 +301,10 @@ struct RevCtx {
 
 // Euler-Maruyama reverse step on Lam = dt lam (the loss-side constants in cx are scaled alike),
 // lam_n = lam' + dt J(y)^T lam'.
-template <int VFORM, bool CHECK>
-__device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc, const Stage<0> &B,
-                                            int t, int64_t n, const RevCtx &cx, float add_w,
-                                            Rev &r)
+template <int VFORM, bool CHECK, int NB>
+__device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc,
+                                            const Stage<0, NB> &B, int t, int64_t n,
+                                            const RevCtx &cx, float add_w, Rev &r)
 {
     if (CHECK && !VFORM && n + 1 == cx.wb)
         r.lx -= cx.jscale;  // the window-start position enters J with weight -1/(W dt)
@@ -368,8 +370,9 @@ __device__ __forceinline__ void add_terms(Rev &r, float c, float v, float e, flo
 }
 
 template <bool CHECK>
-__device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc, const Stage<1> &B,
-                                              int t, int64_t n, const RevCtx &cx, Rev &r)
+__device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc,
+                                              const Stage<1, 8> &B, int t, int64_t n,
+                                              const RevCtx &cx, Rev &r)
 {
     if (CHECK && n + 1 == cx.wb)
         r.lx -= cx.jscale;
@@ -388,9 +391,9 @@ __device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc, 
     r.le = fmaf(h, me + pe, r.le);
 }
 
-template <int SCHEME, int VFORM, bool CHECK>
-__device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const Stage<SCHEME> &B,
-                                         int t, int64_t n, const RevCtx &cx, float add_w, Rev &r)
+template <int SCHEME, int VFORM, bool CHECK, class ST>
+__device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const ST &B, int t,
+                                         int64_t n, const RevCtx &cx, float add_w, Rev &r)
 {
     if constexpr (SCHEME == 0)
         rev_slot_em<VFORM, CHECK>(k, rc, B, t, n, cx, add_w, r);
@@ -399,41 +402,40 @@ __device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const
 }
 
 // Reverse the first `hi` slots of a staged sub-window starting at absolute step base, last first.
-template <int SCHEME, int VFORM, bool CHECK>
-__device__ __forceinline__ void rev_window(const Coef &k, const RevCoef &rc,
-                                           const Stage<SCHEME> &B, int64_t base, int hi,
-                                           const RevCtx &cx, float add_w, Rev &r)
+template <int SCHEME, int VFORM, bool CHECK, class ST>
+__device__ __forceinline__ void rev_window(const Coef &k, const RevCoef &rc, const ST &B,
+                                           int64_t base, int hi, const RevCtx &cx, float add_w,
+                                           Rev &r)
 {
 #pragma unroll
-    for (int t = Stage<SCHEME>::B - 1; t >= 0; --t)
+    for (int t = ST::B - 1; t >= 0; --t)
         if (t < hi)
             rev_slot<SCHEME, VFORM, CHECK>(k, rc, B, t, base + t, cx, add_w, r);
 }
 
 // Recompute the first `hi` slots of the sub-window starting at absolute step base from q,
 // staging them into B.
-template <int SCHEME, bool FROM_LDS>
+template <int SCHEME, bool FROM_LDS, class ST>
 __device__ __forceinline__ void rec_window(const Coef &k, const Stream &s, uint32_t pid,
-                                           Particle &q, int64_t base, int hi, Stage<SCHEME> &B,
+                                           Particle &q, int64_t base, int hi, ST &B,
                                            const float *zl)
 {
     Noise4 z;
     float xb = q.xf + k.phi;
 #pragma unroll
-    for (int t = 0; t < Stage<SCHEME>::B; ++t)
+    for (int t = 0; t < ST::B; ++t)
         if (t < hi)
             rec_slot<SCHEME, FROM_LDS>(k, s, pid, q, xb, z, base, t, B, zl);
 }
 
 // One pipeline trip: reverse window m from R while recomputing window m-1 (from q) into W. The
 // sub-window holding the loss-window start (m == m_chk) runs the two halves one after the other.
-template <int SCHEME, int VFORM, bool FROM_LDS>
+template <int SCHEME, int VFORM, bool FROM_LDS, class ST>
 __device__ __forceinline__ void trip(const Coef &k, const RevCoef &rc, const Stream &s,
                                      uint32_t pid, Particle &q, int64_t m, int64_t m_chk,
-                                     const RevCtx &cx, const Stage<SCHEME> &R, Stage<SCHEME> &W,
-                                     const float *zl, Rev &r)
+                                     const RevCtx &cx, const ST &R, ST &W, const float *zl, Rev &r)
 {
-    constexpr int kB = Stage<SCHEME>::B;
+    constexpr int kB = ST::B;
     if (m == m_chk) {
         rev_window<SCHEME, VFORM, true>(k, rc, R, m * kB, kB, cx, 0.0f, r);
         rec_window<SCHEME, FROM_LDS>(k, s, pid, q, (m - 1) * kB, kB, W, zl);
@@ -451,12 +453,11 @@ __device__ __forceinline__ void trip(const Coef &k, const RevCoef &rc, const Str
 }
 
 // Reverse a whole staged window with no recomputation beside it.
-template <int SCHEME, int VFORM>
+template <int SCHEME, int VFORM, class ST>
 __device__ __forceinline__ void last_window(const Coef &k, const RevCoef &rc, int64_t m,
-                                            int64_t m_chk, const RevCtx &cx,
-                                            const Stage<SCHEME> &R, Rev &r)
+                                            int64_t m_chk, const RevCtx &cx, const ST &R, Rev &r)
 {
-    constexpr int kB = Stage<SCHEME>::B;
+    constexpr int kB = ST::B;
     if (m == m_chk) {
         rev_window<SCHEME, VFORM, true>(k, rc, R, m * kB, kB, cx, 0.0f, r);
     } else {
@@ -481,10 +482,11 @@ __device__ __forceinline__ void flush(Rev &r, double (&A64)[kSums])
 // reversed from one staging buffer, window m-1 is recomputed into the other, in the same
 // instruction stream, so the two dependency chains fill each other's latency (the adjoint runs
 // at one wavefront per SIMD for 2^16-particle ensembles).
-template <int SCHEME, int VFORM, bool ZLDS>
+template <int SCHEME, int VFORM, bool ZLDS, int NB>
 __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
 {
-    constexpr int kStage = Stage<SCHEME>::B;
+    using ST = Stage<SCHEME, NB>;
+    constexpr int kStage = NB;
     extern __shared__ float zbuf[];  // ZLDS: [waves per block][z_slots][64]
     Lane L;
     if (!locate(a, L))
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
         for (int64_t m = m0; m < m1; ++m) {
             put_state(sub + (size_t)(m - m0) * 7 * N, N, L.g, p[0]);
             if constexpr (ZLDS)
-                level1_window<SCHEME>(k, s, pid[0], p[0], m * kStage,
+                level1_window<SCHEME, NB>(k, s, pid[0], p[0], m * kStage,
                                       zl + (size_t)(m - m0) * kStage * 64);
             else
                 advance<SCHEME, 1, 1>(k, s, pid, p, step, (m + 1) * kStage);
@@ -542,7 +544,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
         if (j > 0)
             ck = get_state(a.ckpt + (size_t)(j - 1) * 7 * N, N, L.g);
 
-        Stage<SCHEME> SA, SB;
+        ST SA, SB;
         Particle q = p[0];
         int64_t m = m1;
         const int hi1 = (int)(s1 - m1 * kStage);
@@ -657,18 +659,23 @@ __global__ __launch_bounds__(64) void k_adj_finalize(AdjArgs a, int32_t phase)
 
 using namespace abp;
 
-// LDS one 256-thread block of the backward kernel may take for its noise copy: the smaller of the
-// per-block limit and the CU's LDS, so that a CU still holds its four wavefronts (one per SIMD).
+// LDS limits of the current device: per block, and per CU (what the resident blocks share).
+static size_t lds_attribute(hipDeviceAttribute_t which)
+{
+    int dev = 0, value = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&value, which, dev) != hipSuccess)
+        return 0;
+    return (size_t)value;
+}
+
 static size_t lds_per_block_limit()
 {
-    int dev = 0, per_block = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
-            hipSuccess ||
-        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
-            hipSuccess)
-        return 0;
-    return (size_t)(per_block < per_cu ? per_block : per_cu);
+    return lds_attribute(hipDeviceAttributeMaxSharedMemoryPerBlock);
+}
+
+static size_t lds_per_cu_limit()
+{
+    return lds_attribute(hipDeviceAttributeMaxSharedMemoryPerMultiprocessor);
 }
 
 extern "C" size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set, int64_t n_steps,
@@ -692,7 +699,9 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         cfg->n_steps > kMaxStepIndex || cfg->window < 1 || cfg->window > cfg->n_steps ||
         cfg->ckpt_every < 1 || cfg->lookback < 0 ||
         (cfg->scheme != ABP_EM && cfg->scheme != ABP_HEUN) ||
-        (cfg->scheme == ABP_HEUN && cfg->lookback > 0))
+        (cfg->scheme == ABP_HEUN && cfg->lookback > 0) ||
+        (cfg->stage_steps != 0 && cfg->stage_steps != 8 && cfg->stage_steps != 16) ||
+        (cfg->scheme == ABP_HEUN && cfg->stage_steps == 16))
         return ABP_E_ARG;
     for (int32_t k = 0; k < n_sets; ++k)
         if (!params_ok(h_params[k]) || !(h_params[k].D > 0.0))
@@ -767,25 +776,42 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         else
             hipLaunchKernelGGL(k_adj_forward<0>, dim3(grid), dim3(256), 0, st, a);
     } else {
-        // level-1 noise in LDS when four wavefronts of it fit in one CU's LDS (and one block's
-        // share is allowed); else it is regenerated
-        const int B = heun ? Stage<1>::B : Stage<0>::B;
+        // B = 16 (Euler-Maruyama default) stages in ~350 VGPRs: one wavefront per SIMD. B = 8
+        // fits two (Euler-Maruyama on request; always for Heun, whose stage is larger).
+        const int B = heun ? 8 : (cfg->stage_steps == 8 ? 8 : 16);
+        const int blocks_per_cu = (!heun && B == 8) ? 2 : 1;
+        // level-1 noise in LDS when every resident block's copy fits (and one block's share is
+        // allowed); else it is regenerated
         a.z_slots = (int32_t)(a.K - B);
         const size_t z_bytes = sizeof(float) * 64 * (size_t)a.z_slots * 4;  // per 256-thread block
-        const bool zlds = a.z_slots > 0 && z_bytes <= lds_per_block_limit();
+        const bool zlds = a.z_slots > 0 && z_bytes * blocks_per_cu <= lds_per_cu_limit() &&
+                          z_bytes <= lds_per_block_limit();
         const size_t lds = zlds ? z_bytes : 0;
-        if (heun && zlds)
-            hipLaunchKernelGGL((k_adj_backward<1, 0, true>), dim3(grid), dim3(256), lds, st, a);
-        else if (heun)
-            hipLaunchKernelGGL((k_adj_backward<1, 0, false>), dim3(grid), dim3(256), 0, st, a);
-        else if (a.vform && zlds)
-            hipLaunchKernelGGL((k_adj_backward<0, 1, true>), dim3(grid), dim3(256), lds, st, a);
-        else if (a.vform)
-            hipLaunchKernelGGL((k_adj_backward<0, 1, false>), dim3(grid), dim3(256), 0, st, a);
-        else if (zlds)
-            hipLaunchKernelGGL((k_adj_backward<0, 0, true>), dim3(grid), dim3(256), lds, st, a);
-        else
-            hipLaunchKernelGGL((k_adj_backward<0, 0, false>), dim3(grid), dim3(256), 0, st, a);
+        const dim3 g3(grid), b3(256);
+        if (heun) {
+            if (zlds)
+                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 8>), g3, b3, lds, st, a);
+            else
+                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 8>), g3, b3, 0, st, a);
+        } else if (B == 8) {
+            if (a.vform && zlds)
+                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 8>), g3, b3, lds, st, a);
+            else if (a.vform)
+                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 8>), g3, b3, 0, st, a);
+            else if (zlds)
+                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 8>), g3, b3, lds, st, a);
+            else
+                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 8>), g3, b3, 0, st, a);
+        } else {
+            if (a.vform && zlds)
+                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 16>), g3, b3, lds, st, a);
+            else if (a.vform)
+                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 16>), g3, b3, 0, st, a);
+            else if (zlds)
+                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 16>), g3, b3, lds, st, a);
+            else
+                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 16>), g3, b3, 0, st, a);
+        }
     }
     if (hipGetLastError() != hipSuccess)
         return ABP_E_HIP;

@@ -53,12 +53,13 @@ def _robust_grad(rows, cfg, ws, loss, clip_q: float) -> torch.Tensor:
 
 
 def adam_ratchet(n_sets: int = 1024, n: int = 1024, steps: int = 50_000, window: int = 10_000,
-                 ckpt: int = 160, iters: int = 50, seed: int = 3, lr: float = 1e-2,
-                 lookback: int = 0, clip_q: float | None = None,
+                 ckpt: int = 80, iters: int = 50, seed: int = 3, lr: float = 1e-2,
+                 lookback: int = 0, clip_q: float | None = None, stage: int = 8,
                  verbose: bool = False) -> AdamResult:
     """lookback > 0 uses the decayed adjoint estimator; clip_q winsorises per-particle gradients.
     Both default to the exact pathwise gradient."""
-    cfg = AdjointConfig(n=n, steps=steps, window=window, ckpt=ckpt, seed=seed, lookback=lookback)
+    cfg = AdjointConfig(n=n, steps=steps, window=window, ckpt=ckpt, seed=seed, lookback=lookback,
+                        stage=stage)
     theta0 = torch.tensor(initial_theta(n_sets, seed), dtype=torch.float64)
     idx = [GRAD_KEYS.index(k) for k in FREE]
     free = theta0[:, idx].clone().requires_grad_(True)
@@ -117,7 +118,8 @@ if __name__ == "__main__":
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--steps", type=int, default=50_000)
     ap.add_argument("--window", type=int, default=10_000)
-    ap.add_argument("--ckpt", type=int, default=160)
+    ap.add_argument("--ckpt", type=int, default=80)
+    ap.add_argument("--stage", type=int, default=8, choices=[0, 8, 16])
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--lookback", type=int, default=0)
@@ -125,7 +127,8 @@ if __name__ == "__main__":
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     r = adam_ratchet(args.sets, args.n, args.steps, args.window, args.ckpt, args.iters, args.seed,
-                     lookback=args.lookback, clip_q=args.clip_q, verbose=not args.quiet)
+                     lookback=args.lookback, clip_q=args.clip_q, stage=args.stage,
+                     verbose=not args.quiet)
     print(json.dumps({"workload": "adjoint-batched-1k", "lookback": args.lookback,
                       "clip_q": args.clip_q, "seconds": r.seconds,
                       "mean_abs_v_start": r.history[0], "mean_abs_v_end": r.history[-1],

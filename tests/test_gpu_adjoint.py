@@ -274,3 +274,37 @@ def test_degenerate_sizes(gpu, orc, scheme, n, S, W, K):
                                atol=1e-5 * np.abs(want).max())
     np.testing.assert_allclose(gp.cpu().numpy()[0], go, rtol=1e-3,
                                atol=1e-5 * np.abs(go).max())
+
+
+def test_eight_step_staging(gpu, orc):
+    """stage = 8 (two wavefronts per SIMD): the same recursion with the FP32 gradient sums grouped
+    in 8-step windows. Bit-identical loss, K-independent gradient, within FP32 rounding of the
+    16-step staging and within 1e-3 of the FP64 adjoint; invalid stagings are rejected."""
+    from paper_1104_2499_amd import adjoint, api
+
+    n_sets, n, S, W = 3, 700, 1000, 200
+    theta = _theta(n_sets, jitter=0.2, seed=14)
+    out = {}
+    for stage, K in ((0, 100), (8, 100), (8, 48), (8, 1000), (8, 16)):
+        cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=K, seed=14, stage=stage)
+        rows = adjoint.param_rows(theta, cfg)
+        ws = adjoint.workspace(n_sets, cfg)
+        loss = adjoint.forward(rows, cfg, ws).cpu().numpy()
+        g = adjoint.backward(rows, cfg, ws, torch.ones(n_sets, dtype=torch.float64))
+        out[(stage, K)] = (loss, g.cpu().numpy())
+    for key in ((8, 48), (8, 1000), (8, 16)):
+        np.testing.assert_array_equal(out[key][1], out[(8, 100)][1])
+    np.testing.assert_array_equal(out[(8, 100)][0], out[(0, 100)][0])
+    np.testing.assert_allclose(out[(8, 100)][1], out[(0, 100)][1], rtol=1e-5,
+                               atol=1e-7 * np.abs(out[(0, 100)][1]).max())
+    for k in range(n_sets):
+        x0, v0, e0 = orc.init_state(n, 14, k)
+        _, go = orc.adjoint(_params(theta[k]), x0, v0, e0, S, W, seed=14, set_id=k)
+        want = go.mean(axis=0)
+        np.testing.assert_allclose(out[(8, 100)][1][k], want, rtol=1e-3,
+                                   atol=1e-6 * np.abs(want).max())
+    for stage, scheme in ((12, "em"), (16, "heun"), (-8, "em")):
+        cfg = adjoint.AdjointConfig(n=64, steps=100, window=10, ckpt=16, stage=stage,
+                                    scheme=scheme)
+        with pytest.raises(api.AbpError, match="ABP_E_ARG"):
+            adjoint.forward(adjoint.param_rows(_theta(1), cfg), cfg, adjoint.workspace(1, cfg))
