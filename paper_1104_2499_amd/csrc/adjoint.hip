@@ -10,7 +10,8 @@
 // its whole state (28 bytes) every K steps. Backward phase: for each segment [jK, (j+1)K) in
 // reverse, the lane restores the checkpoint and recomputes the segment with regenerated Philox
 // noise, leaving sub-checkpoints at absolute multiples of B steps in workspace memory (B = 16 for
-// Euler-Maruyama, 8 for Heun; K is rounded up to a multiple of 16); then, for each sub-window in
+// Euler-Maruyama by default, or 8 so that two wavefronts share a SIMD; 8 for Heun; K is rounded
+// up to a multiple of 16); then, for each sub-window in
 // reverse, it restores the sub-checkpoint, recomputes the sub-window while staging the values the
 // reverse step needs (cos and sin of the phase, v, e at every point where the drift is evaluated,
 // and sigma*xi) in registers, and runs the adjoint recursion backwards over it. When the segment's
