@@ -4,7 +4,6 @@ import numpy as np
 import pytest
 import torch
 
-from conftest import mixed_err  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
