@@ -85,14 +85,19 @@ struct AdjLayout {
 
 // Every lane of every wave (also lanes past a set's last particle) owns one slot in the
 // checkpoint planes: N = n_sets * tiles * 64.
-// Checkpoint interval actually used: the requested K rounded up to a multiple of 16, so that every
-// segment starts on a sub-window boundary of either scheme.
-inline int64_t effective_K(int64_t K) { return (K + kAlign - 1) / kAlign * kAlign; }
+// Checkpoint interval actually used: the requested K (at most S: one segment) rounded up to a
+// multiple of 16, so that every segment starts on a sub-window boundary of either scheme.
+inline int64_t effective_K(int64_t K, int64_t S)
+{
+    K = K < S ? K : S;
+    return (K + kAlign - 1) / kAlign * kAlign;
+}
 
+// Sizes are checked for overflow by the caller (layout_fits).
 inline AdjLayout adj_layout(int32_t n_sets, int64_t n, int64_t S, int64_t K)
 {
     AdjLayout L;
-    K = effective_K(K);
+    K = effective_K(K, S);
     L.n_seg = (S + K - 1) / K;
     L.n_sub = K / kMinStage;
     L.tiles = (n + 63) / 64;
@@ -679,11 +684,22 @@ static size_t lds_per_cu_limit()
     return lds_attribute(hipDeviceAttributeMaxSharedMemoryPerMultiprocessor);
 }
 
+// The checkpoint planes dominate the workspace: 28 bytes x lanes x segments, which can exceed
+// 64-bit sizes for absurd inputs; such sizes are rejected.
+static bool layout_fits(int32_t n_sets, int64_t n, int64_t S, int64_t K)
+{
+    const int64_t Ke = effective_K(K, S);
+    const unsigned __int128 lanes = (unsigned __int128)n_sets * (unsigned __int128)((n + 63) / 64) * 64;
+    const unsigned __int128 slots = (unsigned __int128)((S + Ke - 1) / Ke) + Ke / kMinStage;
+    return lanes * slots * 28u < ((unsigned __int128)1 << 62);
+}
+
 extern "C" size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set, int64_t n_steps,
                                               int64_t ckpt_every)
 {
     if (n_sets < 1 || n_per_set < 1 || n_steps < 1 || ckpt_every < 1 ||
-        (int64_t)n_sets * n_per_set > kMaxParticles || n_steps > kMaxStepIndex)
+        (int64_t)n_sets * n_per_set > kMaxParticles || n_steps > kMaxStepIndex ||
+        !layout_fits(n_sets, n_per_set, n_steps, ckpt_every))
         return 0;
     return adj_layout(n_sets, n_per_set, n_steps, ckpt_every).total;
 }
@@ -713,6 +729,8 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         return ABP_E_ARG;
     if (phase == 1 && (!d_gloss || !d_grad || !aligned(d_gloss, 8) || !aligned(d_grad, 8) ||
                        !aligned(d_grad_particles, 8)))
+        return ABP_E_ARG;
+    if (!layout_fits(n_sets, n_per_set, cfg->n_steps, cfg->ckpt_every))
         return ABP_E_ARG;
     const AdjLayout L = adj_layout(n_sets, n_per_set, cfg->n_steps, cfg->ckpt_every);
     if (ws_bytes < L.total)
@@ -761,7 +779,7 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
     a.tiles = L.tiles;
     a.S = cfg->n_steps;
     a.W = cfg->window;
-    a.K = effective_K(cfg->ckpt_every);
+    a.K = effective_K(cfg->ckpt_every, cfg->n_steps);
     const Stream ks = make_stream(cfg->seed, 0);
     a.k0 = ks.k0;
     a.k1 = ks.k1;

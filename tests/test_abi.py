@@ -42,6 +42,19 @@ def test_workspace_queries(lib):
     assert lib.abp_reduce_workspace_bytes(64, 0) >= 16
 
 
+def test_adjoint_workspace_sizes(lib):
+    """28 bytes per lane per checkpoint segment plus the sub-window slots of one segment; a K
+    beyond the run behaves as one segment; sizes past 2^62 bytes are refused (0)."""
+    one = lib.abp_adjoint_workspace_bytes(1, 65536, 10_000, 100)   # K -> 112, 90 segments
+    assert 28 * 65536 * (90 + 14) <= one <= 28 * 65536 * (90 + 14) + 65536 * 100
+    assert lib.abp_adjoint_workspace_bytes(1, 64, 100, 10**15) == \
+        lib.abp_adjoint_workspace_bytes(1, 64, 100, 100)
+    assert lib.abp_adjoint_workspace_bytes(1, 1 << 31, 1 << 34, 16) == 0
+    assert lib.abp_adjoint_workspace_bytes(0, 64, 100, 10) == 0
+    assert lib.abp_adjoint_workspace_bytes(1, 64, 100, 0) == 0
+    assert lib.abp_adjoint_workspace_bytes(1, 64, (1 << 34) + 1, 10) == 0
+
+
 def _state(n=64, ptr=0x1000, id0=0):
     from paper_1104_2499_amd import _lib
 
