@@ -28,6 +28,10 @@
  *  - Results are deterministic: identical inputs give bit-identical outputs for every tuning and
  *    every repeat (FP64 partials are combined in a fixed order; histograms are integer counts).
  *  - Only gfx950 devices are accepted (ABP_E_DEVICE otherwise).
+ *  - abp_init_state, abp_philox, abp_integrate, abp_reduce and abp_reduce_state only enqueue
+ *    kernels (no host synchronisation, no memset), so they may be captured into a HIP graph once
+ *    the first call on the device has run. abp_integrate_batched and abp_adjoint stage host
+ *    tables and wait for them: they cannot be captured.
  */
 #ifndef ABP_H
 #define ABP_H
