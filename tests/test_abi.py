@@ -89,6 +89,7 @@ def test_integrate_rejects_bad_arguments_without_a_device(lib):
     assert call(s_=_state(n=0)) == E_ARG
     assert call(s_=_state(ptr=0x1002)) == E_ARG            # misaligned
     assert call(s_=_state(n=10, id0=0xFFFFFFFF)) == E_ARG   # ids overflow 32 bits
+    assert call(s_=_state(n=(1 << 31) + 1)) == E_ARG        # past the largest ensemble
     bad_p = make_params(dict(D=-0.1))
     assert call(p_=bad_p) == E_ARG
     assert call(p_=make_params(dict(U0=float("inf")))) == E_ARG

@@ -403,3 +403,29 @@ def test_sharding_by_particle_ids(gpu, scheme):
     np.testing.assert_array_equal(parts[0][2] + parts[1][2], _np(full.hist))
     combined = sum(p[1][0] * p[3] for p in parts) / n
     assert abs(combined - full.mean_v) <= 1e-14 * max(1.0, abs(full.mean_v))
+
+
+def test_largest_ensemble(gpu, orc):
+    """The largest ensemble the ABI takes (2^31 particles, 60 GB of state plus a 60 GB window
+    snapshot in HBM), a few Heun steps: sampled particles (tile edges, the last one, random ids)
+    match the oracle and the histogram holds every particle (one particle more is refused before
+    any launch: tests/test_abi.py)."""
+    from paper_1104_2499_amd import api
+
+    n = 1 << 31
+    S, W = 8, 4
+    res = api.run(BASE, n=n, steps=S, window=W, scheme="heun", seed=23, bins=256)
+    assert int(_np(res.hist).sum()) == n
+    assert np.isfinite(res.mean_v) and res.stderr > 0
+    ids = np.unique(np.concatenate([[0, 63, 64, (1 << 30) - 1, 1 << 30, n - 65, n - 64, n - 1],
+                                    np.random.default_rng(1).integers(0, n, 200)]))
+    x0, v0, e0 = orc.init_state(ids.size, 23, ids=ids.astype(np.uint64))
+    x, v, e, _, _ = orc.integrate(BASE, x0, v0, e0, S, scheme=1, seed=23, ids=ids)
+    idx = torch.from_numpy(ids.astype(np.int64)).cuda()
+    st = res.state
+    lo = st.lo[:, idx].double()  # gather first: float64 copies of the whole state would be 51 GB
+    g = (_np((st.cell[idx].double() + st.xf[idx].double()) + lo[0]),
+         _np(st.v[idx].double() + lo[1]), _np(st.e[idx].double() + lo[2]))
+    assert mixed_err(g, (x, v, e)).max() <= 1e-6
+    del res, st
+    torch.cuda.empty_cache()
