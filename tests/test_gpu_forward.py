@@ -126,7 +126,11 @@ def test_deterministic_limit_matches_oracle(gpu, orc):
 
 @pytest.mark.parametrize("params", [dict(U0=0.0, d2=0.0, F0=0.5, D=0.3),
                                     dict(U0=0.3, a=0.4, phi=0.1903, F0=-0.2, d2=1.7, c=0.3,
-                                         q=0.8, gamma0=1.3, D=0.02)])
+                                         q=0.8, gamma0=1.3, D=0.02),
+                                    # no energy input: the depot stays empty (passive limit)
+                                    dict(q=0.0, c=0.0, a=0.0, d2=2.0, D=0.2),
+                                    # no friction: only the depot coupling limits the speed
+                                    dict(gamma0=0.0, d2=1.0, q=2.0, c=0.5, D=0.05)])
 def test_other_parameters(gpu, orc, params):
     res, (x, v, e, xs), (mean, se, hist) = _run_pair(orc, params, 2048, 1000, "em", seed=5)
     err = mixed_err(_gpu_xve(res), (x, v, e))
