@@ -106,6 +106,175 @@ def cpu_baseline(wl: dict, params: dict, seconds_budget: float = 15.0) -> dict:
                       f"{dt_s:.1f} s"}
 
 
+def _host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _gpu_ms(fn, reps: int) -> float:
+    """Median wall time of `fn` in ms (each call synchronised), after one warm-up call."""
+    import numpy as np
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        t.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(t))
+
+
+def _gpu_ensemble_ms(wl: dict, reps: int) -> float:
+    """One whole run of a plain-ensemble workload on the GPU (initial state, integration with the
+    window snapshot and fused reduction, finalize), median ms."""
+    from paper_1104_2499_amd import api
+    from paper_1104_2499_amd.workloads import BASE_PARAMS
+
+    n, S = wl["n"], wl["steps"]
+    state, snap = api.State.empty(n), api.State.empty(n)
+    ws = api.reduce_workspace(n, wl["bins"])
+
+    def run():
+        api.reset_state(state, wl["seed"])
+        api.integrate(state, S, BASE_PARAMS, wl["dt"], wl["scheme"], wl["seed"], 0, 0,
+                      S - wl["window"], snap, ws, wl["bins"])
+        api.reduce(ws, n, wl["bins"], wl["window"] * wl["dt"])
+    return _gpu_ms(run, reps)
+
+
+def cpu_baselines_all() -> list:
+    """The FP64 oracle on every workload, with all host cores and with one, beside the GPU time
+    of the same workload. The oracle runs the whole workload where that takes seconds and an
+    evenly spaced sample of particles (and of parameter sets) otherwise; particles are
+    independent, so its time for the whole workload is the sample's time scaled by work."""
+    import numpy as np
+
+    import oracle
+    from paper_1104_2499_amd import adjoint
+    from paper_1104_2499_amd.optimize import initial_theta
+    from paper_1104_2499_amd.workloads import BASE_PARAMS, WORKLOADS, params_row, sweep_table
+
+    all_cores = oracle.num_threads()
+    out = []
+
+    def timed_cpu(fn, work: float, threads: int, sample: str) -> dict:
+        oracle.set_num_threads(threads)
+        t0 = time.perf_counter()
+        fn()
+        sec = time.perf_counter() - t0
+        oracle.set_num_threads(all_cores)
+        return {"threads": threads, "sample": sample, "particle_steps": work, "seconds": sec,
+                "rate": work / sec}
+
+    def ensemble(wl, n_sample):
+        scheme = oracle.HEUN if wl["scheme"] == "heun" else oracle.EM
+        ids = (np.arange(n_sample, dtype=np.uint64) * (wl["n"] // n_sample)).astype(np.uint32)
+
+        def run():
+            x, v, e = oracle.init_state(n_sample, wl["seed"], ids=ids)
+            xe, _, _, xs, _ = oracle.integrate(BASE_PARAMS, x, v, e, wl["steps"], dt=wl["dt"],
+                                               scheme=scheme, seed=wl["seed"], ids=ids,
+                                               win_begin=wl["steps"] - wl["window"])
+            oracle.reduce(xs, xe, wl["window"] * wl["dt"], wl["bins"])
+        return run, float(n_sample) * wl["steps"]
+
+    # plain ensembles: the parity case in full, the throughput case on a sample
+    for name, n_all, n_one, reps in (("ensemble-1k-em", 1024, 1024, 20),
+                                     ("ensemble-1m-heun", 16384, 512, 2)):
+        wl = WORKLOADS[name]
+        work = float(wl["n"]) * wl["steps"]
+        run, w = ensemble(wl, n_all)
+        cpu = timed_cpu(run, w, all_cores, f"{n_all} of {wl['n']} particles, full steps")
+        run1, w1 = ensemble(wl, n_one)
+        one = timed_cpu(run1, w1, 1, f"{n_one} of {wl['n']} particles, full steps")
+        g_ms = _gpu_ensemble_ms(wl, reps)
+        out.append({"workload": name, "unit": "particle-steps/s", "particle_steps": work,
+                    "gpu_ms": g_ms, "gpu_rate": work / (g_ms * 1e-3), "oracle_all_cores": cpu,
+                    "oracle_one_core": one})
+
+    # parameter sweep: every 64th set with its first 64 trajectories at its full step count
+    wl = WORKLOADS["sweep-4096"]
+    table, n_traj, n_steps = sweep_table(wl["n_sets"], seed=wl["seed"])
+    work = float((n_traj.astype(np.int64) * n_steps).sum())
+
+    def sweep_sample(every, m):
+        sets = range(0, wl["n_sets"], every)
+        w = float(sum(min(int(n_traj[k]), m) * int(n_steps[k]) for k in sets))
+
+        def run():
+            for k in sets:
+                n, S = min(int(n_traj[k]), m), int(n_steps[k])
+                x, v, e = oracle.init_state(n, wl["seed"], k)
+                xe, _, _, xs, _ = oracle.integrate(params_row(table, k), x, v, e, S, dt=wl["dt"],
+                                                   seed=wl["seed"], set_id=k,
+                                                   win_begin=S - S // 2)
+                oracle.reduce(xs, xe, (S // 2) * wl["dt"], wl["bins"])
+        return run, w
+
+    run, w = sweep_sample(64, 64)
+    cpu = timed_cpu(run, w, all_cores, "64 sets (every 64th), first 64 trajectories each")
+    run1, w1 = sweep_sample(256, 16)
+    one = timed_cpu(run1, w1, 1, "16 sets (every 256th), first 16 trajectories each")
+    g_ms = sweep_bench(reps=1)["ms"]
+    out.append({"workload": "sweep-4096", "unit": "particle-steps/s", "particle_steps": work,
+                "gpu_ms": g_ms, "gpu_rate": work / (g_ms * 1e-3), "oracle_all_cores": cpu,
+                "oracle_one_core": one})
+
+    # adjoint: forward + pathwise gradient of the window mean velocity
+    wl = WORKLOADS["adjoint-64k"]
+
+    def adj_sample(wl, n, params):
+        """oracle.adjoint (forward with the trajectory stored, then the reverse sweep) on n
+        evenly spaced particles of set 0."""
+        ids = (np.arange(n, dtype=np.uint64) * (wl["n"] // n)).astype(np.uint32)
+
+        def run():
+            x, v, e = oracle.init_state(n, wl["seed"], 0, ids=ids)
+            oracle.adjoint(params, x, v, e, wl["steps"], wl["window"], dt=wl["dt"],
+                           seed=wl["seed"], ids=ids)
+        return run, float(n) * wl["steps"]
+
+    work = float(wl["n"]) * wl["steps"]
+    run, w = adj_sample(wl, wl["n"], BASE_PARAMS)
+    cpu = timed_cpu(run, w, all_cores, "all 65536 particles")
+    run1, w1 = adj_sample(wl, 1024, BASE_PARAMS)
+    one = timed_cpu(run1, w1, 1, "1024 of 65536 particles")
+    a = adjoint_bench(reps=5)
+    g_ms = a["adjoint_forward_ms"] + a["adjoint_backward_ms"]
+    out.append({"workload": "adjoint-64k", "unit": "particle-steps/s (forward + gradient)",
+                "particle_steps": work, "gpu_ms": g_ms, "gpu_rate": work / (g_ms * 1e-3),
+                "oracle_all_cores": cpu, "oracle_one_core": one})
+
+    # batched adjoint: one Adam iteration's forward + gradients, sampled on set 0
+    wl = WORKLOADS["adjoint-batched-1k"]
+    theta = initial_theta(wl["n_sets"], wl["seed"])
+    p0 = dict(BASE_PARAMS)
+    p0.update({k: float(theta[0, i]) for i, k in enumerate(adjoint.GRAD_KEYS)})
+    work = float(wl["n_sets"]) * wl["n"] * wl["steps"]
+    run, w = adj_sample(wl, wl["n"], p0)
+    cpu = timed_cpu(run, w, all_cores, "set 0 of 1024 (all its 1024 particles)")
+    run1, w1 = adj_sample(wl, 64, p0)
+    one = timed_cpu(run1, w1, 1, "64 evenly spaced particles of set 0")
+    b = adjoint_batched_bench(wl["stage"], wl["ckpt"], reps=2)
+    g_ms = b["forward_ms"] + b["backward_ms"]
+    out.append({"workload": "adjoint-batched-1k", "unit": "particle-steps/s (forward + gradient)",
+                "particle_steps": work, "gpu_ms": g_ms, "gpu_rate": work / (g_ms * 1e-3),
+                "oracle_all_cores": cpu, "oracle_one_core": one})
+
+    for r in out:
+        r["host_cpu"] = _host_cpu()
+        r["gpu_over_oracle_all_cores"] = r["gpu_rate"] / r["oracle_all_cores"]["rate"]
+    return out
+
+
 def sweep_bench(reps: int = 2, tune_batched=None, tune_single=None) -> dict:
     """The 4096-set ratchet sweep in one persistent launch, and the single-set throughput of the
     same scheme (2^20 particles of the base parameters) for comparison; each with its launch
@@ -269,7 +438,15 @@ def main() -> int:
                     help="checkpoint intervals for --adjoint-only (default: the workload's)")
     ap.add_argument("--adjoint-batched", action="store_true",
                     help="only one batched-adjoint iteration per (staging, K) variant")
+    ap.add_argument("--cpu-baselines", action="store_true",
+                    help="only the FP64 oracle on every workload (all host cores and one) beside "
+                         "the GPU time of the same workload, one JSON line each")
     args = ap.parse_args()
+
+    if args.cpu_baselines:
+        for r in cpu_baselines_all():
+            print(json.dumps(r), flush=True)
+        return 0
 
     if args.adjoint_batched:
         for stage, ckpt in ((16, 160), (8, 80), (8, 160), (16, 80)):

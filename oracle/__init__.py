@@ -105,6 +105,11 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Use n threads in later calls (timing only; results do not depend on it)."""
+    _load().orc_set_num_threads(int(n))
+
+
 def philox(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
     """Philox4x32-10 of each row: ctr [m,4] u32, key [m,2] u32 -> [m,4] u32."""
     ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)

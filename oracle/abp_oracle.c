@@ -496,3 +496,14 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of later parallel regions (timing single-core against all-core). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

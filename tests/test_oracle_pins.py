@@ -404,3 +404,22 @@ def test_decayed_adjoint_limits_and_ou_closed_form(orc):
             total += np.sum((r * rho) ** (k - 1 - m) * xi[m]) * dsig
         assert gd[i, 2] == pytest.approx(total / W, rel=1e-9, abs=1e-12)
         assert abs(gd[i, 4]) < 1e-15 and abs(gd[i, 5]) < 1e-15
+
+
+def test_thread_count_does_not_change_results(orc):
+    """The oracle's OpenMP split is over independent particles: one thread and all threads give
+    the same bits (the single-core timings rely on it)."""
+    x, v, e = orc.init_state(96, 5)
+    ref = orc.integrate(None, x, v, e, 300, scheme=orc.HEUN, seed=5, win_begin=100)
+    J0, g0 = orc.adjoint(None, x, v, e, 200, 50, seed=5)
+    n = orc.num_threads()
+    orc.set_num_threads(1)
+    try:
+        one = orc.integrate(None, x, v, e, 300, scheme=orc.HEUN, seed=5, win_begin=100)
+        J1, g1 = orc.adjoint(None, x, v, e, 200, 50, seed=5)
+    finally:
+        orc.set_num_threads(n)
+    for a, b in zip(ref, one):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(J0, J1)
+    np.testing.assert_array_equal(g0, g1)
