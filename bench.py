@@ -36,9 +36,9 @@ VALU_LANE_INSTR_PER_S = N_SIMD * 64 * CLOCK_HZ / 4
 FLOP_PER_STEP = dict(em=24, heun=48)
 TRANS_PER_STEP = dict(em=3, heun=4)
 # VALU instructions per particle-step in the hot loop of k_integrate<scheme, 1, 1> (gfx950 ISA,
-# one Philox block = 4 steps per loop trip: EM 133, Heun 193; SQ_INSTS_VALU of a profiled run
+# one Philox block = 4 steps per loop trip: EM 130, Heun 190; SQ_INSTS_VALU of a profiled run
 # agrees to 0.02%).
-VALU_INSTR_PER_STEP = dict(em=133 / 4, heun=193 / 4)
+VALU_INSTR_PER_STEP = dict(em=130 / 4, heun=190 / 4)
 # Issue time of v_cos/v_sin/v_log/v_sqrt_f32 per wave64 instruction per SIMD, measured by
 # ubench/valu_rates.hip (profiles/valu_issue_rates.txt).
 TRANS_NS_PER_WAVE_INSTR = 3.43

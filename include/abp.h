@@ -87,10 +87,12 @@ typedef struct abp_run {
 
 /* Particle state in structure-of-arrays form, device memory. Sec. 2 of the paper asks single
  * precision to avoid adding very small numbers to very big ones; the state is therefore kept as
- * FP32 high/low pairs: x = cell + xf + lx with an integer cell and xf in [0, 1), v = v + lv,
- * e = e + le. d_lo holds 3n floats: lx at [0, n), lv at [n, 2n), le at [2n, 3n). The low parts
- * are part of the state (a run split into calls is bit-identical to one call only if they are
- * carried). Particle i has Philox id id0 + i. */
+ * FP32 high/low pairs: x = cell + xf + lx with an integer cell, v = v + lv, e = e + le. The
+ * integrator keeps xf in [-1/2, 1/2] (it moves the nearest integer into the cell every four
+ * steps, exactly while |xf| < 2^23; the initial state has xf in [0, 1)). d_lo holds 3n floats:
+ * lx at [0, n), lv at [n, 2n), le at [2n, 3n). The low parts are part of the state (a run split
+ * into calls is bit-identical to one call only if they are carried). Particle i has Philox id
+ * id0 + i. */
 typedef struct abp_state {
     int32_t *d_cell;  /* n */
     float *d_xf;      /* n */

@@ -122,9 +122,9 @@ __device__ __forceinline__ void drift(const Coef &k, float xs, float v, float e,
 // small increments to large values): x = cell + xf + lx, v = v + lv, e = e + le.
 // Within an aligned block of four steps the high parts (cell, xf, v, e) stay fixed and every
 // increment goes into the low part, which starts the block holding the previous rounding error;
-// after the block's last step each pair is renormalised by Fast2Sum (exact: the high part
-// dominates) and xf is wrapped back into [0, 1) with its rounding error kept in lx. The drift sees
-// the rounded sums (high + low). A state stored mid-block is resumed bit for bit.
+// after the block's last step each pair is renormalised by Fast2Sum (exact whenever the high part
+// is the larger) and the nearest integer of xf moves into the cell, exactly. The drift sees the
+// rounded sums (high + low). A state stored mid-block is resumed bit for bit.
 // ---------------------------------------------------------------------------------------------
 struct Particle {
     int32_t cell;
@@ -175,18 +175,19 @@ __device__ __forceinline__ void renorm(float &hi, float &lo)
     hi = t;
 }
 
-// End of an aligned block (after absolute step 4b+3): renormalise the pairs, then move the integer
-// part of xf into the cell; x leaves [0, 1) by at most a few |v| dt per block and cos is periodic.
+// End of an aligned block (after absolute step 4b+3): renormalise the pairs, then move the nearest
+// integer of xf into the cell, leaving xf in [-1/2, 1/2]. For a binary float |x| < 2^23 the
+// difference x - rint(x) is exactly representable (it keeps bits of x below the units place), so
+// the wrap loses nothing and needs no error term. x leaves [-1/2, 1/2] by at most a few |v| dt per
+// block, and cos (in revolutions) is periodic.
 __device__ __forceinline__ void end_block(Particle &p)
 {
     renorm(p.xf, p.lx);
     renorm(p.v, p.lv);
     renorm(p.e, p.le);
-    const float fl = floorf(p.xf);
-    const float w = p.xf - fl;
-    p.lx += p.xf - (w + fl);  // Fast2Sum error of xf + (-fl), |fl| >= |xf| whenever fl != 0
-    p.xf = w;
-    p.cell += (int32_t)fl;
+    const float r = __builtin_rintf(p.xf);
+    p.xf -= r;
+    p.cell += (int32_t)r;
 }
 
 __device__ __forceinline__ float pick(const Noise4 &n, uint32_t j)
