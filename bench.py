@@ -419,8 +419,8 @@ def adjoint_batched_bench(stage: int, ckpt: int, reps: int = 3) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="ensemble-1m-heun",
                     choices=["ensemble-1m-heun", "ensemble-1k-em"])
     ap.add_argument("--sim-steps", type=int, default=None,
@@ -531,7 +531,9 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    kern_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+    kern_all = [a.elapsed_time(b) for a, b in ev]
+    kern_ms = sum(kern_all) / len(kern_all)
+    kern_sd = (sum((t - kern_ms) ** 2 for t in kern_all) / max(1, len(kern_all) - 1)) ** 0.5
     ps = n * S
     value = ps * args.steps / wall
     scheme = wl["scheme"]
@@ -562,6 +564,7 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic, "kernel": kernel, "kernel_ms": kern_ms,
+                     "kernel_ms_sd": kern_sd,
                      "flop_per_particle_step": FLOP_PER_STEP[scheme],
                      "valu_issue": {"instr_per_particle_step": VALU_INSTR_PER_STEP[scheme],
                                     "lane_instr_per_s": lane_instr,
