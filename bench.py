@@ -36,9 +36,14 @@ VALU_LANE_INSTR_PER_S = N_SIMD * 64 * CLOCK_HZ / 4
 FLOP_PER_STEP = dict(em=24, heun=48)
 TRANS_PER_STEP = dict(em=3, heun=4)
 # VALU instructions per particle-step in the hot loop of k_integrate<scheme, 1, 1> (gfx950 ISA,
-# one Philox block = 4 steps per loop trip: EM 130, Heun 190; SQ_INSTS_VALU of a profiled run
-# agrees to 0.02%).
-VALU_INSTR_PER_STEP = dict(em=130 / 4, heun=190 / 4)
+# one Philox block = 4 steps per loop trip: EM 128, Heun 188; SQ_INSTS_VALU of a profiled run
+# gives 128.04 and 188.03 per block).
+VALU_INSTR_PER_STEP = dict(em=128 / 4, heun=188 / 4)
+# FP32 FLOPs per particle-step as the hardware counts them (SQ_INSTS_VALU_FLOPS_FP32: FMA = 2,
+# add, mul and transcendental = 1), including the high/low bookkeeping and Box-Muller: Heun
+# measured (equal to the ISA's 72 FMA, 45 add, 14 mul, 16 transcendental per block); EM from its
+# ISA by the same rule (36 FMA, 29 add, 10 mul, 12 transcendental per block).
+COUNTED_FLOP_PER_STEP = dict(em=30.75, heun=54.75)
 # Issue time of v_cos/v_sin/v_log/v_sqrt_f32 per wave64 instruction per SIMD, measured by
 # ubench/valu_rates.hip (profiles/valu_issue_rates.txt).
 TRANS_NS_PER_WAVE_INSTR = 3.43
@@ -566,6 +571,8 @@ def main() -> int:
                      "traffic": traffic, "kernel": kernel, "kernel_ms": kern_ms,
                      "kernel_ms_sd": kern_sd,
                      "flop_per_particle_step": FLOP_PER_STEP[scheme],
+                     "counted_flop_per_particle_step": COUNTED_FLOP_PER_STEP[scheme],
+                     "counted_tflops": COUNTED_FLOP_PER_STEP[scheme] * kern_rate / 1e12,
                      "valu_issue": {"instr_per_particle_step": VALU_INSTR_PER_STEP[scheme],
                                     "lane_instr_per_s": lane_instr,
                                     "frac_of_one_wave_instr_per_4_cycles":
