@@ -55,6 +55,25 @@ def build_ubench(verbose: bool = False) -> str:
     return UBENCH_BIN
 
 
+ROOT = os.path.dirname(PKG)
+CLIENT_SRC = os.path.join(ROOT, "tests", "c_client", "abi_client.cpp")
+CLIENT_BIN = os.path.join(ROOT, "tests", "c_client", "abi_client")
+
+
+def build_client(verbose: bool = False) -> str:
+    """A host program that uses libabp through include/abp.h alone (the C ABI test client); it
+    finds libabp.so through an rpath relative to itself."""
+    cmd = [hipcc(), "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), CLIENT_SRC,
+           "-L", PKG, "-labp", "-Wl,-rpath,$ORIGIN/../../paper_1104_2499_amd", "-o", CLIENT_BIN]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+    return CLIENT_BIN
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
     print(build_ubench(verbose=True))
+    print(build_client(verbose=True))

@@ -1,0 +1,122 @@
+// abi_client.cpp -- a host program that drives libabp through its C ABI alone (include/abp.h and
+// the HIP runtime's C API; no Python, no torch). It allocates the state, snapshot, reduction
+// workspace and outputs with hipMalloc, runs the initial condition, one integration call with the
+// window snapshot and fused reduction, and the finalize, then prints one JSON line with the
+// results and the status of a call that must be rejected.
+//
+// usage: abi_client n steps window scheme(0 = EM, 1 = Heun) seed
+#include <hip/hip_runtime_api.h>
+
+#include <cstdio>
+#include <cstdlib>
+
+#include "abp.h"
+
+#define HIP_OK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            std::fprintf(stderr, "%s failed: %s\n", #call, hipGetErrorString(e_));     \
+            std::exit(2);                                                              \
+        }                                                                              \
+    } while (0)
+
+#define ABP_OK_OR_EXIT(call)                                                           \
+    do {                                                                               \
+        abp_status s_ = (call);                                                        \
+        if (s_ != ABP_OK) {                                                            \
+            std::fprintf(stderr, "%s failed: %s\n", #call, abp_status_str(s_));        \
+            std::exit(3);                                                              \
+        }                                                                              \
+    } while (0)
+
+static abp_state make_state(int64_t n)
+{
+    abp_state s = {};
+    HIP_OK(hipMalloc((void **)&s.d_cell, sizeof(int32_t) * n));
+    HIP_OK(hipMalloc((void **)&s.d_xf, sizeof(float) * n));
+    HIP_OK(hipMalloc((void **)&s.d_v, sizeof(float) * n));
+    HIP_OK(hipMalloc((void **)&s.d_e, sizeof(float) * n));
+    HIP_OK(hipMalloc((void **)&s.d_lo, sizeof(float) * 3 * n));
+    s.n = n;
+    s.id0 = 0;
+    return s;
+}
+
+static void free_state(abp_state &s)
+{
+    HIP_OK(hipFree(s.d_cell));
+    HIP_OK(hipFree(s.d_xf));
+    HIP_OK(hipFree(s.d_v));
+    HIP_OK(hipFree(s.d_e));
+    HIP_OK(hipFree(s.d_lo));
+}
+
+int main(int argc, char **argv)
+{
+    if (argc != 6) {
+        std::fprintf(stderr, "usage: %s n steps window scheme seed\n", argv[0]);
+        return 1;
+    }
+    const int64_t n = std::atoll(argv[1]);
+    const int64_t steps = std::atoll(argv[2]);
+    const int64_t window = std::atoll(argv[3]);
+    const int32_t scheme = std::atoi(argv[4]);
+    const uint64_t seed = std::strtoull(argv[5], nullptr, 10);
+    const int32_t bins = 256;
+    const double dt = 1e-3;
+
+    HIP_OK(hipSetDevice(0));
+    abp_state s = make_state(n), snap = make_state(n);
+    const size_t ws_bytes = abp_reduce_workspace_bytes(n, bins);
+    void *d_ws = nullptr;
+    double *d_out = nullptr;
+    uint64_t *d_hist = nullptr;
+    HIP_OK(hipMalloc(&d_ws, ws_bytes));
+    HIP_OK(hipMalloc((void **)&d_out, 2 * sizeof(double)));
+    HIP_OK(hipMalloc((void **)&d_hist, bins * sizeof(uint64_t)));
+
+    // the base ratchet: U0, a, phi, gamma0, F0, d2, q, c, D
+    const abp_params p = {1.0, 0.25, 0.0, 1.0, 0.0, 1.0, 1.0, 0.1, 0.1};
+    abp_run r = {};
+    r.dt = dt;
+    r.n_steps = steps;
+    r.step0 = 0;
+    r.win_begin = steps - window;
+    r.seed = seed;
+    r.set_id = 0;
+    r.scheme = scheme;
+
+    ABP_OK_OR_EXIT(abp_init_state(&s, seed, 0, nullptr));
+    ABP_OK_OR_EXIT(abp_integrate(&p, &r, &s, &snap, d_ws, ws_bytes, bins, nullptr, nullptr));
+    ABP_OK_OR_EXIT(abp_reduce(d_ws, n, bins, (double)window * dt, d_out, d_hist, nullptr));
+
+    double out[2];
+    uint64_t hist[bins];
+    HIP_OK(hipMemcpy(out, d_out, sizeof out, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(hist, d_hist, sizeof hist, hipMemcpyDeviceToHost));
+    uint64_t total = 0;
+    for (int b = 0; b < bins; ++b)
+        total += hist[b];
+
+    // a negative step count is rejected before anything is enqueued
+    abp_run bad = r;
+    bad.n_steps = -1;
+    const abp_status rejected = abp_integrate(&p, &bad, &s, &snap, d_ws, ws_bytes, bins, nullptr,
+                                              nullptr);
+    // so is a workspace one byte short
+    const abp_status short_ws = abp_integrate(&p, &r, &s, &snap, d_ws, ws_bytes - 1, bins,
+                                              nullptr, nullptr);
+
+    std::printf("{\"abi_version\": %d, \"mean_v\": %.17g, \"stderr\": %.17g, \"hist_total\": %llu, "
+                "\"hist_first\": %llu, \"rejected\": \"%s\", \"short_workspace\": \"%s\"}\n",
+                abp_abi_version(), out[0], out[1], (unsigned long long)total,
+                (unsigned long long)hist[0], abp_status_str(rejected), abp_status_str(short_ws));
+
+    HIP_OK(hipFree(d_ws));
+    HIP_OK(hipFree(d_out));
+    HIP_OK(hipFree(d_hist));
+    free_state(s);
+    free_state(snap);
+    return 0;
+}

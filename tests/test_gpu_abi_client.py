@@ -1,0 +1,39 @@
+"""The C ABI from a plain host program (tests/c_client/abi_client.cpp: include/abp.h and the HIP
+runtime's C API, no Python binding, no torch): its results equal the Python binding's bit for bit
+and invalid calls are rejected with the documented statuses. The client runs as a child process,
+started before this process touches the GPU."""
+import json
+import os
+import subprocess
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+CLIENT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c_client", "abi_client")
+
+
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_c_client_equals_python_binding(scheme):
+    n, steps, window, seed = 5000, 3000, 1000, 11
+    assert os.path.exists(CLIENT), "the C ABI client is built by build()"
+    print(f"abi_client {n} {steps} {window} {scheme} {seed}", flush=True)
+    proc = subprocess.run([CLIENT, str(n), str(steps), str(window),
+                           "0" if scheme == "em" else "1", str(seed)],
+                          capture_output=True, text=True, timeout=120)
+    assert proc.returncode == 0, proc.stderr
+    got = json.loads(proc.stdout.strip().splitlines()[-1])
+
+    import torch
+
+    assert torch.cuda.is_available(), "gpu-marked test needs a HIP device"
+    from paper_1104_2499_amd import api
+    from paper_1104_2499_amd.workloads import BASE_PARAMS
+
+    res = api.run(BASE_PARAMS, n=n, steps=steps, window=window, scheme=scheme, seed=seed,
+                  bins=256)
+    assert got["abi_version"] == 1
+    assert got["mean_v"] == res.mean_v and got["stderr"] == res.stderr
+    assert got["hist_total"] == n and got["hist_first"] == int(res.hist[0])
+    assert got["rejected"] == "invalid argument"
+    assert got["short_workspace"] == "workspace too small"
