@@ -12,6 +12,10 @@ the first repeats discarded (Sec. 3 runs 20 and averages the last 15), for sever
 including zero steps; the per-step cost is the slope of a least-squares line of time against the
 step count and the offset its intercept (Sec. 3.2, Fig. 6 methodology). On MI355X the "bands" the
 paper saw on a 9800 GT are expected at multiples of the resident capacity.
+
+density_cost(): cost of the time-accumulated histogram of x mod 1 (the particle density the paper
+displays while the ensemble runs, Sec. 2) against the sampling stride: one integration call with
+and without sampling, its time per sample and per sampled particle.
 """
 from __future__ import annotations
 
@@ -80,11 +84,48 @@ def scaling(sizes, steps=(0, 1000, 10_000), scheme: str = "em", repeats: int = 2
     return rows
 
 
+def density_cost(strides=(0, 10_000, 1000, 100, 10, 1), n: int = 1 << 20, steps: int = 20_000,
+                 scheme: str = "heun", bins: int = 256, repeats: int = 5) -> list[dict]:
+    """Median time (ms, HIP events around the integration call) of n particles x `steps` steps
+    with the x mod 1 histogram accumulated every `stride` absolute steps (0 = off), and the
+    extra time per sample over the unsampled call."""
+    stream = torch.cuda.current_stream()
+    state = api.State.empty(n)
+    acc = torch.zeros(bins, dtype=torch.int64, device=state.cell.device)
+    rows, base_ms = [], None
+    for stride in strides:
+        times = []
+        for _ in range(repeats + 1):
+            api.reset_state(state, 1, 0, stream)
+            acc.zero_()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            api.integrate(state, steps, BASE_PARAMS, scheme=scheme, seed=1, stream=stream,
+                          hist_stride=stride, hist_acc=acc if stride else None)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times[1:]))
+        samples = steps // stride if stride else 0
+        total = int(acc.sum().item())
+        row = {"stride": stride, "samples": samples, "ms": ms, "counts_ok": total == n * samples}
+        if stride == 0:
+            base_ms = ms
+        elif base_ms is not None:
+            row["extra_ms"] = ms - base_ms
+            row["extra_us_per_sample"] = (ms - base_ms) * 1e3 / samples
+            row["extra_ps_per_particle_sample"] = (ms - base_ms) * 1e9 / (samples * n)
+        rows.append(row)
+    return rows
+
+
 if __name__ == "__main__":
     import argparse
 
-    ap = argparse.ArgumentParser(description="load-force curve and scaling experiment")
-    ap.add_argument("what", choices=["force", "scaling"])
+    ap = argparse.ArgumentParser(description="load-force curve, scaling and density-sampling "
+                                             "experiments")
+    ap.add_argument("what", choices=["force", "scaling", "density"])
     ap.add_argument("--quick", action="store_true")
     args = ap.parse_args()
     if args.what == "force":
@@ -97,6 +138,9 @@ if __name__ == "__main__":
             print(json.dumps({"F0": round(float(f), 4), "mean_v": float(v), "stderr": float(s),
                               "load_power": float(p), "efficiency": float(eta)}))
         print(json.dumps({"seconds": secs}))
+    elif args.what == "density":
+        for row in density_cost():
+            print(json.dumps(row), flush=True)
     else:
         sizes = [2 ** k for k in range(0, 21)]
         if not args.quick:

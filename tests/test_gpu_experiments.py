@@ -39,3 +39,15 @@ def test_scaling_measurement_shape(gpu):
     for r in rows:
         assert r["t0_us"] > 0 and r["t400_us"] > r["t0_us"]
         assert r["us_per_step"] > 0
+
+
+def test_density_cost_measurement_shape(gpu):
+    """The density-sampling measurement: every sampled histogram holds n x samples counts,
+    including a stride that ends calls inside Philox blocks."""
+    from paper_1104_2499_amd import experiments
+
+    rows = experiments.density_cost(strides=(0, 100, 7), n=4096, steps=700, repeats=2)
+    assert [r["stride"] for r in rows] == [0, 100, 7]
+    assert [r["samples"] for r in rows] == [0, 7, 100]
+    assert all(r["counts_ok"] for r in rows)
+    assert all("extra_us_per_sample" in r for r in rows[1:])
