@@ -11,17 +11,17 @@
 // reverse, the lane restores the checkpoint and recomputes the segment with regenerated Philox
 // noise, leaving sub-checkpoints at absolute multiples of B steps in workspace memory (B = 16 for
 // Euler-Maruyama by default, or 8 so that two wavefronts share a SIMD; 8 for Heun; K is rounded
-// up to a multiple of 16); then, for each sub-window in
-// reverse, it restores the sub-checkpoint, recomputes the sub-window while staging the values the
-// reverse step needs (cos and sin of the phase, v, e at every point where the drift is evaluated,
-// and sigma*xi) in registers, and runs the adjoint recursion backwards over it. When the segment's
-// noise fits in LDS (K - B steps x 64 lanes x 4 bytes per wavefront, four wavefronts per CU),
-// level 1 keeps each sigma*xi it draws there and the staged recomputation reads it back instead of
-// running Philox and Box-Muller a second time. The recomputation reproduces the
-// forward bits exactly (the integrator's state is resumable mid-block), so the result does not
-// depend on K. Per-step gradient terms are summed in FP32 within each absolute B-step window and
-// in FP64 across windows (that grouping does not depend on K either); tiles of 64 particles and
-// sets are then reduced in a fixed order.
+// up to a multiple of 16). Then, for each sub-window in reverse, it restores the sub-checkpoint,
+// recomputes the sub-window while staging the values the reverse step needs (cos and sin of the
+// phase, v, e at every point where the drift is evaluated, and sigma*xi) in registers, and runs
+// the adjoint recursion backwards over it. When the segment's noise fits in LDS (K - B steps x 64
+// lanes x 4 bytes per wavefront; one four-wavefront block per CU with 16-step staging, two with
+// 8-step staging), level 1 keeps each sigma*xi it draws there and the staged recomputation reads
+// it back instead of running Philox and Box-Muller a second time. The recomputation reproduces
+// the forward bits exactly (the integrator's state is resumable mid-block), so the result does
+// not depend on K. Per-step gradient terms are summed in FP32 within each absolute B-step window
+// and in FP64 across windows (that grouping does not depend on K either); tiles of 64 particles
+// and sets are then reduced in a fixed order.
 //
 // Workspace layout (abp_adjoint_workspace_bytes):
 //   AdjRow rows[n_sets] | float ckpt[n_seg][7][N] | float sub[K/8][7][N] |
