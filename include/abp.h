@@ -55,7 +55,10 @@ typedef enum abp_status {
 
 typedef enum abp_scheme { ABP_EM = 0, ABP_HEUN = 1 } abp_scheme;
 
-/* Model parameters of Eqs. (1)-(3). D >= 0 (D = 0 is the deterministic limit). */
+/* Model parameters of Eqs. (1)-(3). D >= 0 (D = 0 is the deterministic limit). The kernels compute
+ * in FP32: a call is rejected (ABP_E_ARG) unless every coefficient derived from the parameters and
+ * the time step (2 pi U0, 8 pi U0 a, F0 + 4 pi U0 a, gamma0, d2, q, c, phi, dt, 2 D dt; for the
+ * adjoint also 4 pi U0, 4 pi^2 U0 dt, 1 / (2D), ...) is finite in FP32 and dt is positive in FP32. */
 typedef struct abp_params {
     double U0, a, phi, gamma0, F0, d2, q, c, D;
 } abp_params;

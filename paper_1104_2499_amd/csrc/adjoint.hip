@@ -704,6 +704,38 @@ extern "C" size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set,
     return adj_layout(n_sets, n_per_set, n_steps, ckpt_every).total;
 }
 
+// Per-set constants of both phases, from the FP64 parameters.
+static AdjRow make_adj_row(const abp_params &p, double dt)
+{
+    AdjRow r;
+    std::memset(&r, 0, sizeof r);
+    r.k = make_coef(p, dt);
+    r.r.two_pi = (float)(2.0 * kPi);
+    r.r.four_pi_U0 = (float)(4.0 * kPi * p.U0);
+    r.r.a2 = (float)(2.0 * p.a);
+    r.r.eight_a = (float)(8.0 * p.a);
+    r.r.m4pi2U0 = (float)(-4.0 * kPi * kPi * p.U0);
+    r.r.inv2D = (float)(1.0 / (2.0 * p.D));
+    r.r.m4pi2U0_dt = (float)(-4.0 * kPi * kPi * p.U0 * dt);
+    r.r.d2_dt = (float)(p.d2 * dt);
+    r.r.g0_dt = (float)(p.gamma0 * dt);
+    r.r.c_dt = (float)(p.c * dt);
+    r.r.m2d2_dt = (float)(-2.0 * p.d2 * dt);
+    return r;
+}
+
+// Every FP32 constant of the row is finite (a tiny D makes 1 / (2D) overflow, for instance).
+static bool adj_row_ok(const AdjRow &r)
+{
+    const RevCoef &c = r.r;
+    const float f[] = {c.two_pi, c.four_pi_U0, c.a2, c.eight_a, c.m4pi2U0, c.inv2D,
+                       c.m4pi2U0_dt, c.d2_dt, c.g0_dt, c.c_dt, c.m2d2_dt};
+    for (float x : f)
+        if (!std::isfinite(x))
+            return false;
+    return coef_ok(r.k);
+}
+
 extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_params *h_params,
                                   int64_t n_per_set, const abp_adjoint_cfg *cfg, void *d_ws,
                                   size_t ws_bytes, double *d_loss, const double *d_gloss,
@@ -721,7 +753,8 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         (cfg->scheme == ABP_HEUN && cfg->stage_steps == 16))
         return ABP_E_ARG;
     for (int32_t k = 0; k < n_sets; ++k)
-        if (!params_ok(h_params[k]) || !(h_params[k].D > 0.0))
+        if (!params_ok(h_params[k]) || !(h_params[k].D > 0.0) ||
+            !adj_row_ok(make_adj_row(h_params[k], cfg->dt)))
             return ABP_E_ARG;
     if (!d_ws || !aligned(d_ws, 256))
         return ABP_E_ARG;
@@ -739,23 +772,8 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         return st;
 
     std::vector<AdjRow> rows((size_t)n_sets);
-    for (int32_t k = 0; k < n_sets; ++k) {
-        const abp_params &p = h_params[k];
-        AdjRow &r = rows[(size_t)k];
-        std::memset(&r, 0, sizeof r);
-        r.k = make_coef(p, cfg->dt);
-        r.r.two_pi = (float)(2.0 * kPi);
-        r.r.four_pi_U0 = (float)(4.0 * kPi * p.U0);
-        r.r.a2 = (float)(2.0 * p.a);
-        r.r.eight_a = (float)(8.0 * p.a);
-        r.r.m4pi2U0 = (float)(-4.0 * kPi * kPi * p.U0);
-        r.r.inv2D = (float)(1.0 / (2.0 * p.D));
-        r.r.m4pi2U0_dt = (float)(-4.0 * kPi * kPi * p.U0 * cfg->dt);
-        r.r.d2_dt = (float)(p.d2 * cfg->dt);
-        r.r.g0_dt = (float)(p.gamma0 * cfg->dt);
-        r.r.c_dt = (float)(p.c * cfg->dt);
-        r.r.m2d2_dt = (float)(-2.0 * p.d2 * cfg->dt);
-    }
+    for (int32_t k = 0; k < n_sets; ++k)
+        rows[(size_t)k] = make_adj_row(h_params[k], cfg->dt);
     hipStream_t st = as_stream(stream);
     char *ws = reinterpret_cast<char *>(d_ws);
     if (hipMemcpyAsync(ws + L.rows, rows.data(), sizeof(AdjRow) * rows.size(),

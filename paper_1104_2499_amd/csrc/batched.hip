@@ -188,7 +188,8 @@ extern "C" abp_status abp_integrate_batched(int32_t n_sets, const abp_params *h_
     for (int32_t k = 0; k < n_sets; ++k) {
         const int64_t S = h_nsteps[k];
         const int64_t W = h_window ? h_window[k] : S / 2;
-        if (!params_ok(h_params[k]) || S < 1 || S > kMaxStepIndex || W < 1 || W > S)
+        if (!params_ok(h_params[k]) || !coef_ok(make_coef(h_params[k], cfg->dt)) || S < 1 ||
+            S > kMaxStepIndex || W < 1 || W > S)
             return ABP_E_ARG;
     }
     Shape sh;

@@ -56,6 +56,18 @@ inline Coef make_coef(const abp_params &p, double dt)
     return k;
 }
 
+// The kernels compute with the FP32 coefficients: a parameter set and time step are accepted only
+// if every coefficient is finite after the conversion and the FP32 time step is positive (finite
+// FP64 values can overflow FP32, and a tiny dt can round to zero).
+inline bool coef_ok(const Coef &k)
+{
+    const float f[] = {k.dt, k.half_dt, k.bm, k.phi, k.K1, k.B, k.FH, k.g0, k.d2, k.q, k.c};
+    for (float x : f)
+        if (!std::isfinite(x))
+            return false;
+    return k.dt > 0.0f;
+}
+
 inline Stream make_stream(uint64_t seed, uint32_t set)
 {
     Stream s;

@@ -260,7 +260,8 @@ extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const
 {
     if (!p || !r || !state_ok(s) || !params_ok(*p))
         return ABP_E_ARG;
-    if (!(r->dt > 0.0) || !is_finite(r->dt) || r->n_steps < 0 || r->step0 < 0 ||
+    if (!(r->dt > 0.0) || !is_finite(r->dt) || !coef_ok(make_coef(*p, r->dt)) || r->n_steps < 0 ||
+        r->step0 < 0 ||
         r->n_steps > kMaxStepIndex || r->step0 + r->n_steps > kMaxStepIndex || r->win_begin < -1 ||
         (r->scheme != ABP_EM && r->scheme != ABP_HEUN) || r->hist_stride < 0)
         return ABP_E_ARG;

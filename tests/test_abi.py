@@ -144,3 +144,40 @@ def test_other_entry_points_validate(lib):
     b = _state()
     assert lib.abp_reduce_state(ctypes.byref(a), ctypes.byref(b), 256, 0x10000, 8,
                                 None) == _lib.ABP_E_WORKSPACE
+
+
+def test_parameters_that_overflow_fp32_are_rejected(lib):
+    """The kernels run on FP32 coefficients: finite FP64 values that overflow FP32 (or a time
+    step that rounds to zero, or 1 / (2D) past the FP32 range in the adjoint) are invalid
+    arguments, reported before anything is enqueued (no device is needed to see that)."""
+    from paper_1104_2499_amd import _lib
+    from paper_1104_2499_amd.api import make_params
+
+    E_ARG = _lib.ABP_E_ARG
+    s = _state()
+    run = _lib.AbpRun(1e-3, 100, 0, -1, 42, 0, 0)
+    bad_params = [dict(U0=1e39), dict(d2=1e39), dict(F0=3.5e38), dict(gamma0=-1e39),
+                  dict(D=1e300)]
+    for bad in bad_params:
+        p = make_params(bad)
+        assert lib.abp_integrate(ctypes.byref(p), ctypes.byref(run), ctypes.byref(s), None, None,
+                                 0, 0, None, None) == E_ARG, bad
+    tiny_dt = _lib.AbpRun(1e-50, 100, 0, -1, 42, 0, 0)
+    p = make_params()
+    assert lib.abp_integrate(ctypes.byref(p), ctypes.byref(tiny_dt), ctypes.byref(s), None, None,
+                             0, 0, None, None) == E_ARG
+
+    # batched: one bad set among good ones
+    table = (_lib.AbpParams * 3)(make_params(), make_params(dict(U0=1e39)), make_params())
+    ntraj = (ctypes.c_int32 * 3)(64, 64, 64)
+    nsteps = (ctypes.c_int64 * 3)(100, 100, 100)
+    cfg = _lib.AbpBatch(1e-3, 11, 0, 0)
+    assert lib.abp_integrate_batched(3, table, ntraj, nsteps, None, ctypes.byref(cfg), None,
+                                     0x10000, 1 << 30, 0x1000, None, None) == E_ARG
+
+    # adjoint: D so small that 1 / (2D) overflows FP32, and a huge U0
+    acfg = _lib.AbpAdjointCfg(1e-3, 100, 20, 16, 42, 0, 0, 0)
+    for bad in (dict(D=1e-40), dict(U0=1e38)):
+        p1 = (_lib.AbpParams * 1)(make_params(bad))
+        assert lib.abp_adjoint(0, 1, p1, 64, ctypes.byref(acfg), 0x10000, 1 << 30, 0x1000, None,
+                               None, None, None) == E_ARG, bad
