@@ -8,11 +8,10 @@ from __future__ import annotations
 import ctypes
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from . import _lib
-import numpy as np
-
 from .workloads import BASE_PARAMS, PARAM_KEYS
 
 SCHEMES = {"em": _lib.ABP_EM, "heun": _lib.ABP_HEUN}

@@ -225,6 +225,7 @@ extern "C" abp_status abp_integrate_batched(int32_t n_sets, const abp_params *h_
 
     hipStream_t st = as_stream(stream);
     char *ws = reinterpret_cast<char *>(d_ws);
+    WaitOnExit wait{st, true};  // rows and items are read by the copies below
     if (hipMemcpyAsync(ws + L.rows, rows.data(), sizeof(SetRow) * rows.size(),
                        hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(ws + L.items, items.data(), sizeof(Item) * items.size(),
@@ -265,5 +266,6 @@ extern "C" abp_status abp_integrate_batched(int32_t n_sets, const abp_params *h_
     if (hipGetLastError() != hipSuccess)
         return ABP_E_HIP;
     // the staged tables live in pageable host memory owned by this call
+    wait.armed = false;
     return hipStreamSynchronize(st) == hipSuccess ? ABP_OK : ABP_E_HIP;
 }

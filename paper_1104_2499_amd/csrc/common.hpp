@@ -25,6 +25,18 @@ inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_
 
 inline bool is_finite(double x) { return std::isfinite(x); }
 
+// Waits for a stream when it leaves scope once armed: host tables that queued copies read from
+// must outlive those copies on every return path, error returns included.
+struct WaitOnExit {
+    hipStream_t st;
+    bool armed;
+    ~WaitOnExit()
+    {
+        if (armed)
+            (void)hipStreamSynchronize(st);
+    }
+};
+
 inline bool params_ok(const abp_params &p)
 {
     return is_finite(p.U0) && is_finite(p.a) && is_finite(p.phi) && is_finite(p.gamma0) && is_finite(p.F0) &&
