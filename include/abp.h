@@ -21,6 +21,8 @@
  *  - Pointers named d_* are HIP device memory owned by the caller; h_* are host memory; structs
  *    passed by pointer are host memory read during the call only. The library never frees or
  *    keeps caller memory after returning, allocates no device memory, and never prints.
+ *  - Alignment: workspaces (d_ws) 256 bytes, which hipMalloc returns; FP64 and u64 arrays 8 bytes;
+ *    FP32, int32 and u32 arrays 4 bytes. A misaligned pointer is ABP_E_ARG.
  *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the null stream). The
  *    status is returned synchronously: arguments are validated before anything is enqueued, and
  *    on ABP_E_ARG / ABP_E_WORKSPACE / ABP_E_DEVICE nothing is written. ABP_E_HIP reports a
