@@ -208,10 +208,11 @@ typedef struct abp_adjoint_cfg {
                             biased, bounded-variance estimator for long chaotic horizons) */
     int32_t scheme;      /* ABP_EM or ABP_HEUN: the map whose discrete adjoint is taken */
     int32_t stage_steps; /* steps the backward pass stages in registers at a time: 0 = default
-                            (16 for Euler-Maruyama, 8 for Heun); 8 lets two wavefronts share a
-                            SIMD (faster for ensembles of more than ~2 wavefronts per SIMD);
-                            16 is Euler-Maruyama only. Changes the grouping of the FP32 gradient
-                            sums, not the recursion */
+                            (16), or 8 or 16. For Euler-Maruyama 8 lets two wavefronts share a
+                            SIMD (faster for ensembles of more than ~2 wavefronts per SIMD); the
+                            Heun backward runs one wavefront per SIMD either way and is faster
+                            at 16. Changes the grouping of the FP32 gradient sums, not the
+                            recursion */
 } abp_adjoint_cfg;
 
 /* Bytes of workspace: checkpoints (28 bytes per particle per segment), sub-checkpoints, and the

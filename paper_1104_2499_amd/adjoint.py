@@ -32,7 +32,7 @@ class AdjointConfig:
     seed: int = 42
     lookback: int = 0         # 0 = exact gradient; T > 0 = sensitivities damped by (1 - 1/T)/step
     scheme: str = "em"        # "em" or "heun" (lookback > 0 needs "em")
-    stage: int = 0            # backward register staging: 0 = default, 8 = two wavefronts/SIMD
+    stage: int = 0            # backward register staging: 0 = default (16); 8 = two EM wavefronts/SIMD
     fixed: dict = field(default_factory=lambda: {"phi": BASE_PARAMS["phi"]})
 
     def abi(self) -> _lib.AbpAdjointCfg:

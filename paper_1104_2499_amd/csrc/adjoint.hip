@@ -9,9 +9,9 @@
 // Forward phase: each lane integrates its particle from the workload initial condition and stores
 // its whole state (28 bytes) every K steps. Backward phase: for each segment [jK, (j+1)K) in
 // reverse, the lane restores the checkpoint and recomputes the segment with regenerated Philox
-// noise, leaving sub-checkpoints at absolute multiples of B steps in workspace memory (B = 16 for
-// Euler-Maruyama by default, or 8 so that two wavefronts share a SIMD; 8 for Heun; K is rounded
-// up to a multiple of 16). Then, for each sub-window in reverse, it restores the sub-checkpoint,
+// noise, leaving sub-checkpoints at absolute multiples of B steps in workspace memory (B = 16 by
+// default, or 8: for Euler-Maruyama that lets two wavefronts share a SIMD; K is rounded up to a
+// multiple of 16). Then, for each sub-window in reverse, it restores the sub-checkpoint,
 // recomputes the sub-window while staging the values the reverse step needs (cos and sin of the
 // phase, v, e at every point where the drift is evaluated, and sigma*xi) in registers, and runs
 // the adjoint recursion backwards over it. When the segment's noise fits in LDS (K - B steps x 64
@@ -204,8 +204,9 @@ __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
 // Values of one sub-window staged for the reverse sweep, per step: cos and sin of the phase
 // 2 pi (x + phi), v and e (the rounded sums the drift saw), sigma xi; for Heun also the same at
 // the predictor point.
-// NB = steps per sub-window: 16 or 8 for Euler-Maruyama (8 stages half the registers, so that
-// two wavefronts fit one SIMD), 8 for Heun.
+// NB = steps per sub-window, 16 or 8. For Euler-Maruyama 8 stages half the registers, so that two
+// wavefronts fit one SIMD; the Heun kernel holds one wavefront per SIMD either way (~320 VGPRs at
+// 8, the full 512 with a few spilled at 16), and 16 halves the per-window overheads.
 template <int SCHEME, int NB>
 struct Stage;
 
@@ -215,9 +216,9 @@ struct Stage<0, NB> {
     float c[B], s[B], v[B], e[B], z[B];
 };
 
-template <>
-struct Stage<1, 8> {
-    static constexpr int B = 8;
+template <int NB>
+struct Stage<1, NB> {
+    static constexpr int B = NB;
     float c[B], s[B], v[B], e[B], ct[B], st[B], vt[B], et[B], z[B];
 };
 
@@ -375,9 +376,9 @@ __device__ __forceinline__ void add_terms(Rev &r, float c, float v, float e, flo
     r.A[8] += wv;
 }
 
-template <bool CHECK>
+template <bool CHECK, int NB>
 __device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc,
-                                              const Stage<1, 8> &B, int t, int64_t n,
+                                              const Stage<1, NB> &B, int t, int64_t n,
                                               const RevCtx &cx, Rev &r)
 {
     if (CHECK && n + 1 == cx.wb)
@@ -749,8 +750,7 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         cfg->ckpt_every < 1 || cfg->lookback < 0 ||
         (cfg->scheme != ABP_EM && cfg->scheme != ABP_HEUN) ||
         (cfg->scheme == ABP_HEUN && cfg->lookback > 0) ||
-        (cfg->stage_steps != 0 && cfg->stage_steps != 8 && cfg->stage_steps != 16) ||
-        (cfg->scheme == ABP_HEUN && cfg->stage_steps == 16))
+        (cfg->stage_steps != 0 && cfg->stage_steps != 8 && cfg->stage_steps != 16))
         return ABP_E_ARG;
     for (int32_t k = 0; k < n_sets; ++k)
         if (!params_ok(h_params[k]) || !(h_params[k].D > 0.0) ||
@@ -815,7 +815,7 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
     } else {
         // B = 16 (Euler-Maruyama default) stages in ~350 VGPRs: one wavefront per SIMD. B = 8
         // fits two (Euler-Maruyama on request; always for Heun, whose stage is larger).
-        const int B = heun ? 8 : (cfg->stage_steps == 8 ? 8 : 16);
+        const int B = cfg->stage_steps == 8 ? 8 : 16;
         const int blocks_per_cu = (!heun && B == 8) ? 2 : 1;
         // level-1 noise in LDS when every resident block's copy fits (and one block's share is
         // allowed); else it is regenerated
@@ -825,7 +825,12 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
                           z_bytes <= lds_per_block_limit();
         const size_t lds = zlds ? z_bytes : 0;
         const dim3 g3(grid), b3(256);
-        if (heun) {
+        if (heun && B == 16) {
+            if (zlds)
+                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 16>), g3, b3, lds, st, a);
+            else
+                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 16>), g3, b3, 0, st, a);
+        } else if (heun) {
             if (zlds)
                 hipLaunchKernelGGL((k_adj_backward<1, 0, true, 8>), g3, b3, lds, st, a);
             else
