@@ -252,11 +252,19 @@ def cpu_baselines_all() -> list:
     cpu = timed_cpu(run, w, all_cores, "all 65536 particles")
     run1, w1 = adj_sample(wl, 1024, BASE_PARAMS)
     one = timed_cpu(run1, w1, 1, "1024 of 65536 particles")
+
+    def plain():  # the oracle's forward alone on the same ensemble, for its own cost ratio
+        x, v, e = oracle.init_state(wl["n"], wl["seed"])
+        oracle.integrate(BASE_PARAMS, x, v, e, wl["steps"], dt=wl["dt"], seed=wl["seed"],
+                         win_begin=wl["steps"] - wl["window"])
+    fwd = timed_cpu(plain, work, all_cores, "all 65536 particles, forward only")
     a = adjoint_bench(reps=5)
     g_ms = a["adjoint_forward_ms"] + a["adjoint_backward_ms"]
     out.append({"workload": "adjoint-64k", "unit": "particle-steps/s (forward + gradient)",
                 "particle_steps": work, "gpu_ms": g_ms, "gpu_rate": work / (g_ms * 1e-3),
-                "oracle_all_cores": cpu, "oracle_one_core": one})
+                "gpu_cost_ratio": a["cost_ratio"], "oracle_all_cores": cpu,
+                "oracle_one_core": one, "oracle_forward_seconds": fwd["seconds"],
+                "oracle_cost_ratio": cpu["seconds"] / fwd["seconds"]})
 
     # batched adjoint: one Adam iteration's forward + gradients, sampled on set 0
     wl = WORKLOADS["adjoint-batched-1k"]
