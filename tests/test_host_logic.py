@@ -1,4 +1,8 @@
 """Host-side marshalling logic (no GPU): parameter rows, configurations, projections."""
+import os
+import subprocess
+import sys
+
 import numpy as np
 import pytest
 import torch
@@ -90,3 +94,44 @@ def test_tuner_cache_roundtrip(tmp_path, monkeypatch):
     blocker.write_text("x")
     monkeypatch.setenv("ABP_TUNE_CACHE", str(blocker / "tune.json"))
     assert tune._store_cache({"k": {}}) is False
+
+
+def _fresh_python(code: str) -> subprocess.CompletedProcess:
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    return subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root,
+                          timeout=300)
+
+
+def test_missing_library_fails_loudly():
+    """Without libabp.so the product path raises LibraryMissing; there is no CPU or torch
+    fallback that would compute something instead."""
+    code = (
+        "import paper_1104_2499_amd._lib as L\n"
+        "L._lib = None\n"
+        "L.load.__defaults__ = ('/nonexistent/libabp.so',)\n"
+        "from paper_1104_2499_amd import api\n"
+        "try:\n"
+        "    api.run(None, n=64, steps=10, window=5, device='cpu')\n"
+        "except L.LibraryMissing as e:\n"
+        "    print('raised', type(e).__name__)\n"
+        "else:\n"
+        "    print('computed')\n")
+    res = _fresh_python(code)
+    assert res.returncode == 0, res.stderr[-2000:]
+    assert "raised LibraryMissing" in res.stdout
+
+
+def test_package_never_imports_the_oracle():
+    """The oracle is test infrastructure: importing every module of the package leaves it
+    unimported."""
+    code = (
+        "import glob, importlib, os, sys\n"
+        "import paper_1104_2499_amd as P\n"
+        "for f in sorted(glob.glob(os.path.join(P.__path__[0], '*.py'))):\n"
+        "    name = os.path.basename(f)[:-3]\n"
+        "    if name != '__init__':\n"
+        "        importlib.import_module('paper_1104_2499_amd.' + name)\n"
+        "print('oracle' in sys.modules)\n")
+    res = _fresh_python(code)
+    assert res.returncode == 0, res.stderr[-2000:]
+    assert res.stdout.strip().splitlines()[-1] == "False"
