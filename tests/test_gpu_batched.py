@@ -51,17 +51,19 @@ def test_each_set_equals_its_single_run_for_every_tuning(gpu, scheme):
                         assert torch.equal(r.hist[k], a.hist)
 
 
-def test_sets_match_oracle(gpu, orc):
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_sets_match_oracle(gpu, orc, scheme):
     from paper_1104_2499_amd import api
 
     table, n_traj, n_steps, window, _ = _small_sweep()
-    r = api.sweep(table, n_traj, n_steps, window, scheme="em", seed=11, bins=64)
+    r = api.sweep(table, n_traj, n_steps, window, scheme=scheme, seed=11, bins=64)
     for k in range(len(n_traj)):
         params = {key: float(table[k, i]) for i, key in enumerate(KEYS)}
         n = int(n_traj[k])
         x0, v0, e0 = orc.init_state(n, 11, k)
         x, v, e, xs, _ = orc.integrate(params, x0, v0, e0, int(n_steps[k]), seed=11, set_id=k,
-                                       win_begin=int(n_steps[k] - window[k]))
+                                       win_begin=int(n_steps[k] - window[k]),
+                                       scheme=orc.EM if scheme == "em" else orc.HEUN)
         mean, se, hist = orc.reduce(xs, x, float(window[k]) * 1e-3, 64)
         assert abs(r.mean_v[k] - mean) <= 1e-5 * max(1.0, abs(mean)), k
         assert int(r.hist[k].sum()) == n
