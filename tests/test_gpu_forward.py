@@ -70,6 +70,41 @@ def test_noise_matches_oracle_normals(gpu, orc):
     assert worst <= 1e-6
 
 
+def test_noise_statistics_1e8_samples(gpu):
+    """The kernel's normals as a sample of N(0, 1): 2^24 particles x 6 step indices = 1.0e8
+    values read as in test_noise_matches_oracle_normals. Mean and variance within 5 standard
+    errors, lag-one correlation between consecutive steps of a particle within 5 standard
+    errors of 0, and the Kolmogorov-Smirnov distance to the standard normal CDF below 2.0e-4
+    (the 0.1% critical value 1.95 / sqrt(1e8); the 2^-23 grid of the uniforms caps |z| at 5.65,
+    a tail mass of 1.6e-8)."""
+    from paper_1104_2499_amd import api
+
+    n, seed = 1 << 24, 2024
+    free = dict(U0=0.0, a=0.0, phi=0.0, gamma0=0.0, F0=0.0, d2=0.0, q=0.0, c=0.0, D=1.0)
+    cols = []
+    s = api.State.empty(n)
+    for n0 in (0, 1, 2, 3, 4, 5):
+        api.reset_state(s, seed)
+        api.integrate(s, 1, free, dt=0.5, scheme="em", seed=seed, step0=n0)
+        cols.append(s.v.double() + s.lo[1].double())
+    z = torch.stack(cols)  # [6, n]
+    del s, cols
+    m = z.numel()
+    mean, var = float(z.mean()), float(z.var())
+    assert abs(mean) <= 5 / m ** 0.5, mean
+    assert abs(var - 1.0) <= 5 * (2.0 / m) ** 0.5, var
+    lag = float((z[1:] * z[:-1]).mean())  # consecutive steps of each particle
+    assert abs(lag) <= 5 / (m * 5 / 6) ** 0.5, lag
+    zs, _ = torch.sort(z.flatten())
+    del z
+    cdf = torch.special.ndtr(zs)
+    i = torch.arange(1, m + 1, dtype=torch.float64, device=zs.device)
+    d = float(torch.maximum((i / m - cdf).max(), (cdf - (i - 1) / m).max()))
+    print(f"1e8 normals: mean {mean:.2e}, var-1 {var - 1:.2e}, lag-1 {lag:.2e}, KS D {d:.2e}, "
+          f"max |z| {float(zs.abs().max()):.3f}")
+    assert d < 2.0e-4, d
+
+
 @pytest.mark.parametrize("n,id0,seed,set_id", [(5000, 0, 42, 0), (77, 123456, 2**40 + 5, 9),
                                                 (1, 0xFFFFFFFF, 0, 0)])
 def test_init_state_bit_exact(gpu, orc, n, id0, seed, set_id):
