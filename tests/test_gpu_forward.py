@@ -105,6 +105,41 @@ def test_noise_statistics_1e8_samples(gpu):
     assert d < 2.0e-4, d
 
 
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_closed_forms_at_full_size(gpu, scheme):
+    """With U0 = d2 = 0 the model decouples into closed forms that hold for any ensemble size;
+    checked on 2^20 particles after 5000 steps (F0 = 0.5, gamma0 = 1, D = 0.1, q = 1, c = 0.1,
+    dt = 1e-3, v0 = e0 = 0). Depot: e_n = (q/c)(1 - r^n) with r = 1 - c dt (Euler-Maruyama) or
+    1 - c dt + (c dt)^2 / 2 (Heun), the same for every particle, to 1e-6 relative. Velocity: the
+    discrete Ornstein-Uhlenbeck recursion v' = rho v + b + s xi with, for Euler-Maruyama,
+    rho = 1 - g dt, b = F0 dt, s = sigma, and for Heun rho = 1 - g dt + (g dt)^2 / 2,
+    b = F0 dt (1 - g dt / 2), s = sigma (1 - g dt / 2): mean b (1 - rho^n) / (1 - rho) and
+    variance s^2 (1 - rho^(2n)) / (1 - rho^2), within 5 standard errors of the sample."""
+    from paper_1104_2499_amd import api
+
+    n, S, dt = 1 << 20, 5000, 1e-3
+    g, F0, D, q, c = 1.0, 0.5, 0.1, 1.0, 0.1
+    p = dict(U0=0.0, a=0.0, phi=0.0, gamma0=g, F0=F0, d2=0.0, q=q, c=c, D=D)
+    res = api.run(p, n=n, steps=S, window=S // 2, scheme=scheme, seed=31, bins=0)
+    v = res.state.v64().double()
+    e = res.state.e64().double()
+    sig = (2 * D * dt) ** 0.5
+    if scheme == "em":
+        r, rho, b, s_ = 1 - c * dt, 1 - g * dt, F0 * dt, sig
+    else:
+        r = 1 - c * dt + (c * dt) ** 2 / 2
+        rho, b, s_ = 1 - g * dt + (g * dt) ** 2 / 2, F0 * dt * (1 - g * dt / 2), sig * (1 - g * dt / 2)
+    e_want = q / c * (1 - r ** S)
+    assert float((e - e_want).abs().max()) <= 1e-6 * e_want
+    m_want = b * (1 - rho ** S) / (1 - rho)
+    var_want = s_ ** 2 * (1 - rho ** (2 * S)) / (1 - rho ** 2)
+    m, var = float(v.mean()), float(v.var())
+    print(f"{scheme}: e err {float((e - e_want).abs().max()) / e_want:.1e}; <v> {m:.6f} vs "
+          f"{m_want:.6f}; var {var:.6f} vs {var_want:.6f}")
+    assert abs(m - m_want) <= 5 * (var_want / n) ** 0.5
+    assert abs(var - var_want) <= 5 * var_want * (2.0 / n) ** 0.5
+
+
 @pytest.mark.parametrize("n,id0,seed,set_id", [(5000, 0, 42, 0), (77, 123456, 2**40 + 5, 9),
                                                 (1, 0xFFFFFFFF, 0, 0)])
 def test_init_state_bit_exact(gpu, orc, n, id0, seed, set_id):
