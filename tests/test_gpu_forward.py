@@ -140,24 +140,25 @@ def test_closed_forms_at_full_size(gpu, scheme):
     assert abs(var - var_want) <= 5 * var_want * (2.0 / n) ** 0.5
 
 
-def test_passive_ratchet_boltzmann_at_full_size(gpu):
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_passive_ratchet_boltzmann_at_full_size(gpu, scheme):
     """A passive particle (d2 = F0 = 0) in the ratchet is in equilibrium at temperature D / gamma0:
     the density of x mod 1 is proportional to exp(-gamma0 U(x) / D) and the current vanishes.
-    2^20 particles, U0 = 0.2 (barrier ~0.44), D = 0.5, Euler-Maruyama with dt = 1e-3: 5000 steps
+    2^20 particles, U0 = 0.2 (barrier ~0.44), D = 0.5, dt = 1e-3, both schemes: 5000 steps
     of burn-in, then the time-accumulated histogram (64 bins) every 100 steps for 15000 steps.
-    Total variation from the Boltzmann bin masses < 0.003 (measured 0.0011; shifting the law by
-    one bin moves it by 0.0136, so the check would see such an error) and the mean velocity over
-    the sampling phase within 4 standard errors of 0."""
+    Total variation from the Boltzmann bin masses < 0.003 (measured 0.0011 with Euler-Maruyama;
+    shifting the law by one bin moves it by 0.0136, so the check would see such an error) and
+    the mean velocity over the sampling phase within 4 standard errors of 0."""
     from paper_1104_2499_amd import api
 
     n, burn, S, stride, bins, dt = 1 << 20, 5000, 20000, 100, 64, 1e-3
     U0, a, D, g = 0.2, 0.25, 0.5, 1.0
     p = dict(U0=U0, a=a, phi=0.0, gamma0=g, F0=0.0, d2=0.0, q=1.0, c=0.1, D=D)
     s = api.init_state(n, 13)
-    api.integrate(s, burn, p, dt=dt, scheme="em", seed=13)
+    api.integrate(s, burn, p, dt=dt, scheme=scheme, seed=13)
     x_a = s.x64().clone()
     acc = torch.zeros(bins, dtype=torch.int64, device=x_a.device)
-    api.integrate(s, S - burn, p, dt=dt, scheme="em", seed=13, step0=burn, hist_stride=stride,
+    api.integrate(s, S - burn, p, dt=dt, scheme=scheme, seed=13, step0=burn, hist_stride=stride,
                   hist_acc=acc)
     h = acc.cpu().numpy().astype(np.float64)
     assert h.sum() == n * (S - burn) // stride
@@ -172,7 +173,8 @@ def test_passive_ratchet_boltzmann_at_full_size(gpu):
     disp = (s.x64() - x_a).cpu().numpy()
     T = (S - burn) * dt
     vbar, se = disp.mean() / T, disp.std() / np.sqrt(n) / T
-    print(f"Boltzmann TV {tv:.2e} (one-bin shift {shift:.2e}); <v> {vbar:.2e} +- {se:.1e}")
+    print(f"{scheme}: Boltzmann TV {tv:.2e} (one-bin shift {shift:.2e}); <v> {vbar:.2e} +- "
+          f"{se:.1e}")
     assert tv < 0.003 and shift > 4 * 0.003
     assert abs(vbar) <= 4 * se
 
