@@ -254,6 +254,30 @@ def test_ensemble_parity_1e4_steps(gpu, orc, scheme):
     assert np.abs(hg - hist.astype(np.int64)).sum() <= 2 * (bg != bo).sum()
 
 
+@pytest.mark.parametrize("scheme,order", [("em", 1), ("heun", 2)])
+def test_convergence_order_in_the_deterministic_limit(gpu, orc, scheme, order):
+    """D = 0: the kernel's error at t = 1 against an FP64 RK4 solution (step dt / 100) falls by
+    2^order when dt halves (dt = 1e-2, 5e-3, 2.5e-3): first order for Euler-Maruyama, second
+    for Heun. 256 particles of the base physics from the workload initial condition."""
+    from paper_1104_2499_amd import api
+
+    n, T = 256, 1.0
+    p = dict(BASE, D=0.0)
+    x0, v0, e0 = orc.init_state(n, 3)
+    errs = []
+    for dt in (1e-2, 5e-3, 2.5e-3):
+        S = int(round(T / dt))
+        xr, vr, er = orc.rk4(p, x0, v0, e0, 100 * S, dt / 100)
+        s = api.init_state(n, 3)
+        api.integrate(s, S, p, dt=dt, scheme=scheme, seed=3)
+        err = mixed_err((_np(s.x64()), _np(s.v64()), _np(s.e64())), (xr, vr, er))
+        errs.append(float(np.median(err)))
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    print(f"{scheme}: median errors {errs}, ratios {ratios}")
+    for r in ratios:
+        assert 0.75 * 2 ** order <= r <= 1.3 * 2 ** order, ratios
+
+
 def test_deterministic_limit_matches_oracle(gpu, orc):
     p = dict(BASE, D=0.0)
     res, (x, v, e, xs), _ = _run_pair(orc, p, 256, 2000, "heun")
