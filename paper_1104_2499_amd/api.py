@@ -267,6 +267,8 @@ def sweep(table, n_traj, n_steps, window=None, dt: float = 1e-3, scheme="em", se
     if nt.shape != (n_sets,) or ns.shape != (n_sets,):
         raise ValueError("n_traj and n_steps need one entry per set")
     win = None if window is None else np.ascontiguousarray(window, dtype=np.int64)
+    if win is not None and win.shape != (n_sets,):
+        raise ValueError("window needs one entry per set")
     if ws is None:
         ws = batched_workspace(nt, bins, device)
     out = torch.empty((n_sets, 2), dtype=torch.float64, device=device)

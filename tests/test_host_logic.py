@@ -135,3 +135,29 @@ def test_package_never_imports_the_oracle():
     res = _fresh_python(code)
     assert res.returncode == 0, res.stderr[-2000:]
     assert res.stdout.strip().splitlines()[-1] == "False"
+
+
+def test_python_layer_rejects_bad_arguments_before_any_device_call():
+    """Argument errors the binding itself catches (the C ABI validates the rest): they raise
+    before anything touches a device, so they are checked here without one."""
+    from paper_1104_2499_amd import adjoint, api
+    from paper_1104_2499_amd.workloads import sweep_table
+
+    with pytest.raises(KeyError):
+        api.make_params(dict(U1=1.0))
+    with pytest.raises(ValueError):
+        api.make_tuning("fastest")
+    with pytest.raises(ValueError):
+        api.params_table(np.zeros((3, 8)))
+    with pytest.raises(ValueError):
+        api.run(None, n=64, steps=10, window=11)
+    table, n_traj, n_steps = sweep_table(4, seed=1)
+    with pytest.raises(ValueError):
+        api.sweep(table, n_traj[:3], n_steps)
+    with pytest.raises(ValueError):
+        api.sweep(table, n_traj, n_steps, window=n_steps[:3] // 2)  # one window per set
+    with pytest.raises(ValueError):
+        adjoint.AdjointConfig(n=64, steps=100, window=10, ckpt=16, scheme="rk4").abi()
+    with pytest.raises(ValueError):
+        adjoint.param_rows(torch.zeros((2, 6), dtype=torch.float64),
+                           adjoint.AdjointConfig(n=64, steps=100, window=10, ckpt=16))
