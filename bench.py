@@ -301,6 +301,8 @@ def sweep_bench(reps: int = 2, tune_batched=None, tune_single=None) -> dict:
     wl = WORKLOADS["sweep-4096"]
     table, n_traj, n_steps = sweep_table(wl["n_sets"], seed=wl["seed"])
     work = float((n_traj.astype(np.int64) * n_steps).sum())
+    # lanes past a set's last trajectory in its last 64-particle tile still step (masked)
+    lanes = float(((n_traj.astype(np.int64) + 63) // 64 * 64 * n_steps).sum())
     ws = api.batched_workspace(n_traj, wl["bins"])
     api.sweep(table, n_traj, n_steps, scheme=wl["scheme"], seed=wl["seed"], bins=wl["bins"], ws=ws,
               tune=tune_batched)
@@ -333,6 +335,7 @@ def sweep_bench(reps: int = 2, tune_batched=None, tune_single=None) -> dict:
             "ms": t_sweep * 1e3, "particle_steps": work, "scheme": wl["scheme"],
             "single_set_value": v_single, "single_set_config": f"{n} particles x {S} steps",
             "ratio_to_single_set": v_sweep / v_single,
+            "masked_lane_fraction": 1.0 - work / lanes,
             "finite_sets": int(np.isfinite(r.mean_v).sum())}
 
 
