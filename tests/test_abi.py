@@ -181,3 +181,39 @@ def test_parameters_that_overflow_fp32_are_rejected(lib):
         p1 = (_lib.AbpParams * 1)(make_params(bad))
         assert lib.abp_adjoint(0, 1, p1, 64, ctypes.byref(acfg), 0x10000, 1 << 30, 0x1000, None,
                                None, None, None) == E_ARG, bad
+
+
+def test_ctypes_structs_match_the_c_header(tmp_path):
+    """The binding's ctypes structs have the sizes and field offsets of include/abp.h, as a C
+    compiler lays them out (a mismatch would hand the library shifted arguments)."""
+    import shutil
+    import subprocess
+
+    from paper_1104_2499_amd import _lib
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"abp_params": _lib.AbpParams, "abp_run": _lib.AbpRun, "abp_state": _lib.AbpState,
+               "abp_tuning": _lib.AbpTuning, "abp_batch": _lib.AbpBatch,
+               "abp_adjoint_cfg": _lib.AbpAdjointCfg}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "abp.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {}
+    for line in out.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
