@@ -217,3 +217,38 @@ def test_ctypes_structs_match_the_c_header(tmp_path):
         assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
         for field, _ in py._fields_:
             assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
+
+
+def test_ctypes_signatures_match_the_c_prototypes():
+    """Every binding in _lib.SIGNATURES has the prototype's argument count, and each scalar
+    argument and result the C type's width and signedness (pointers bound as pointers)."""
+    from paper_1104_2499_amd import _lib
+
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    scalar = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "uint32_t": ctypes.c_uint32,
+              "uint64_t": ctypes.c_uint64, "double": ctypes.c_double, "size_t": ctypes.c_size_t,
+              "int": ctypes.c_int, "abp_status": ctypes.c_int}
+
+    def is_pointer_type(t):
+        return t in (ctypes.c_void_p, ctypes.c_char_p) or (
+            isinstance(t, type) and issubclass(t, ctypes._Pointer))
+
+    protos = re.findall(r"\n([A-Za-z_][\w ]*?\*?)\s*\b(abp_\w+)\s*\(([^;]*?)\)\s*;", text)
+    assert len(protos) == len(_lib.SIGNATURES)
+    for ret, name, args in protos:
+        restype, argtypes = _lib.SIGNATURES[name]
+        ret = ret.replace("const", "").strip()
+        if "*" in ret:
+            assert is_pointer_type(restype), name
+        else:
+            assert restype is scalar[ret], (name, ret)
+        args = [a.strip() for a in " ".join(args.split()).split(",")]
+        if args == ["void"]:
+            args = []
+        assert len(args) == len(argtypes), name
+        for a, t in zip(args, argtypes):
+            if "*" in a:
+                assert is_pointer_type(t), (name, a)
+            else:
+                ctype = a.replace("const ", "").rsplit(" ", 1)[0].strip()
+                assert t is scalar[ctype], (name, a)
