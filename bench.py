@@ -47,6 +47,17 @@ COUNTED_FLOP_PER_STEP = dict(em=30.75, heun=54.75)
 # Issue time of v_cos/v_sin/v_log/v_sqrt_f32 per wave64 instruction per SIMD, measured by
 # ubench/valu_rates.hip (profiles/valu_issue_rates.txt).
 TRANS_NS_PER_WAVE_INSTR = 3.43
+# VALU instructions of each issue class per 4-step loop trip of k_integrate<scheme, 1, 1> (gfx950
+# ISA; for Heun equal, class by class, to the SQ_INSTS_VALU_* counters) and the issue time of each
+# class per wave64 instruction per SIMD measured by ubench/valu_rates.hip, in ns: FMA reading
+# three VGPRs, FMA with an SGPR/constant operand, FP32 add/sub and mul, transcendental,
+# v_mad_u64_u32, v_bitop3_b32, and the rest (alignbit, xor, rint, cvt, moves; costed as an integer
+# add).
+LOOP_CLASS_COUNTS = dict(
+    heun=dict(fma3=8, fma=64, add=45, mul=14, trans=16, mad64=15, bitop3=14, other=12),
+    em=dict(fma3=4, fma=32, add=29, mul=10, trans=12, mad64=15, bitop3=14, other=12))
+CLASS_NS = dict(fma3=1.4696, fma=1.0324, add=0.9512, mul=0.9203, trans=3.42, mad64=1.4286,
+                bitop3=1.7187, other=1.0367)
 
 
 KERNEL_SOURCES = ("common.hpp", "device.hpp", "reduce.hpp", "forward.hip")
@@ -558,6 +569,12 @@ def main() -> int:
     kernel = "k_integrate_" + scheme
     traffic = load_traffic(kernel, args.workload)
     lane_instr = VALU_INSTR_PER_STEP[scheme] * kern_rate
+    # issue time the loop's instruction mix needs at the measured class costs, over the time the
+    # SIMDs actually spent: the share of the VALU issue capacity the kernel uses
+    trips_per_simd = ps / 4 / 64 / N_SIMD
+    model_s = trips_per_simd * sum(c * CLASS_NS[k] for k, c in
+                                   LOOP_CLASS_COUNTS[scheme].items()) * 1e-9
+    issue_util = model_s / (kern_ms * 1e-3)
     trans_rate = TRANS_PER_STEP[scheme] * kern_rate
     trans_peak = N_SIMD * 64 / (TRANS_NS_PER_WAVE_INSTR * 1e-9)
     o = out.cpu()
@@ -587,7 +604,8 @@ def main() -> int:
                      "valu_issue": {"instr_per_particle_step": VALU_INSTR_PER_STEP[scheme],
                                     "lane_instr_per_s": lane_instr,
                                     "frac_of_one_wave_instr_per_4_cycles":
-                                        lane_instr / VALU_LANE_INSTR_PER_S},
+                                        lane_instr / VALU_LANE_INSTR_PER_S,
+                                    "class_weighted_utilization": issue_util},
                      "transcendental": {"per_particle_step": TRANS_PER_STEP[scheme],
                                         "per_s": trans_rate, "peak_per_s": trans_peak,
                                         "frac": trans_rate / trans_peak}},
