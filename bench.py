@@ -46,7 +46,7 @@ VALU_INSTR_PER_STEP = dict(em=128 / 4, heun=188 / 4)
 COUNTED_FLOP_PER_STEP = dict(em=30.75, heun=54.75)
 # Issue time of v_cos/v_sin/v_log/v_sqrt_f32 per wave64 instruction per SIMD, measured by
 # ubench/valu_rates.hip (profiles/valu_issue_rates.txt).
-TRANS_NS_PER_WAVE_INSTR = 3.43
+TRANS_NS_PER_WAVE_INSTR = 3.45
 # VALU instructions of each issue class per 4-step loop trip of k_integrate<scheme, 1, 1> (gfx950
 # ISA; for Heun equal, class by class, to the SQ_INSTS_VALU_* counters) and the issue time of each
 # class per wave64 instruction per SIMD measured by ubench/valu_rates.hip, in ns: FMA reading
@@ -56,8 +56,8 @@ TRANS_NS_PER_WAVE_INSTR = 3.43
 LOOP_CLASS_COUNTS = dict(
     heun=dict(fma3=8, fma=64, add=45, mul=14, trans=16, mad64=15, bitop3=14, other=12),
     em=dict(fma3=4, fma=32, add=29, mul=10, trans=12, mad64=15, bitop3=14, other=12))
-CLASS_NS = dict(fma3=1.4696, fma=1.0324, add=0.9512, mul=0.9203, trans=3.42, mad64=1.4286,
-                bitop3=1.7187, other=1.0367)
+CLASS_NS = dict(fma3=1.5315, fma=1.0493, add=0.9959, mul=0.9540, trans=3.4536, mad64=1.4587,
+                bitop3=1.7200, other=1.0500)
 
 
 KERNEL_SOURCES = ("common.hpp", "device.hpp", "reduce.hpp", "forward.hip")
