@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define ABP_ABI_VERSION 1
+#define ABP_ABI_VERSION 2
 
 typedef enum abp_status {
     ABP_OK = 0,
@@ -119,8 +119,9 @@ typedef struct abp_tuning {
 int abp_abi_version(void);
 const char *abp_status_str(abp_status s);
 
-/* Initial condition x0 ~ U[0,1) (24-bit grid), v0 = e0 = 0, of particles id0..id0+n-1 of set
- * `set_id` under `seed` (see the noise contract). */
+/* Initial condition of an ensemble (the paper's work items start from a state the text does not
+ * fix, Sec. 2; here x0 ~ U[0,1) on the 24-bit grid, v0 = e0 = 0) for particles id0..id0+n-1 of
+ * set `set_id` under `seed` (see the noise contract). Writes all of *s (low parts zeroed). */
 abp_status abp_init_state(const abp_state *s, uint64_t seed, uint32_t set_id, void *stream);
 
 /* Philox4x32-10 of m counters: d_ctr [m][4] u32, d_key [m][2] u32 -> d_out [m][4] u32. The
@@ -148,16 +149,19 @@ abp_status abp_integrate(const abp_params *p, const abp_run *r, const abp_state 
                          const abp_state *snap, void *d_ws, size_t ws_bytes, int32_t n_bins,
                          const abp_tuning *tune, void *stream);
 
-/* Finish a reduction left in d_ws by abp_integrate or abp_reduce_state for n particles:
+/* Finish a reduction left in d_ws by abp_integrate or abp_reduce_state for n particles, into the
+ * ensemble quantities the paper computes from the trajectories (Sec. 2: the mean drift velocity
+ * of the ratchet current, and the particle density over one period of the potential):
  * d_out[0] = mean drift velocity = sum(delta) / (n window_time), d_out[1] = its standard error,
  * d_hist[n_bins] = u64 counts of particles with floor(n_bins (x - floor x)) = b (clamped to
  * n_bins - 1), x = (cell + xf) + lx evaluated in FP64; delta is the same FP64 position at the end
- * minus that of the snapshot. d_hist may be NULL when n_bins = 0. */
-abp_status abp_reduce(const void *d_ws, int64_t n, int32_t n_bins, double window_time,
-                      double *d_out, uint64_t *d_hist, void *stream);
+ * minus that of the snapshot. d_hist may be NULL when n_bins = 0. ws_bytes must be at least
+ * abp_reduce_workspace_bytes(n, n_bins) (ABP_E_WORKSPACE otherwise). */
+abp_status abp_reduce(const void *d_ws, size_t ws_bytes, int64_t n, int32_t n_bins,
+                      double window_time, double *d_out, uint64_t *d_hist, void *stream);
 
-/* The reduction stage alone, from two states (window start and end): writes the same partials
- * into d_ws as abp_integrate does. */
+/* The reduction stage alone (the ensemble averages of Sec. 2), from two states (window start and
+ * end): writes the same partials into d_ws as abp_integrate does. */
 abp_status abp_reduce_state(const abp_state *snap, const abp_state *end, int32_t n_bins,
                             void *d_ws, size_t ws_bytes, void *stream);
 

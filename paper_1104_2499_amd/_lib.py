@@ -67,7 +67,7 @@ SIGNATURES = {
     "abp_reduce_workspace_bytes": (_sz, [_i64, _i32]),
     "abp_integrate": (ctypes.c_int, [_P(AbpParams), _P(AbpRun), _P(AbpState), _P(AbpState), _vp,
                                      _sz, _i32, _P(AbpTuning), _vp]),
-    "abp_reduce": (ctypes.c_int, [_vp, _i64, _i32, _f64, _vp, _vp, _vp]),
+    "abp_reduce": (ctypes.c_int, [_vp, _sz, _i64, _i32, _f64, _vp, _vp, _vp]),
     "abp_reduce_state": (ctypes.c_int, [_P(AbpState), _P(AbpState), _i32, _vp, _sz, _vp]),
     "abp_batched_workspace_bytes": (_sz, [_i32, _vp, _i32]),
     "abp_integrate_batched": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _P(AbpBatch),

@@ -185,7 +185,7 @@ def reduce(ws: torch.Tensor, n: int, n_bins: int, window_time: float, stream=Non
     """(mean velocity, standard error) as a float64 [2] tensor and the uint64 histogram."""
     out = torch.empty(2, dtype=torch.float64, device=ws.device)
     hist = torch.empty(max(n_bins, 1), dtype=torch.int64, device=ws.device)
-    check(_lib.load().abp_reduce(_ptr(ws), n, n_bins, window_time, _ptr(out),
+    check(_lib.load().abp_reduce(_ptr(ws), ws.numel(), n, n_bins, window_time, _ptr(out),
                                  _ptr(hist) if n_bins > 0 else None, _stream(stream)),
           "abp_reduce")
     return out, hist[:n_bins]

@@ -637,28 +637,44 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
     }
 }
 
-// One wavefront per set: loss = mean over particles of J_i; grad = gloss / N * sum of tiles.
-__global__ __launch_bounds__(64) void k_adj_finalize(AdjArgs a, int32_t phase)
+// One block of kFinalizeThreads per set: loss = mean over particles of J_i (the same fixed-order
+// combine as the plain integrator's); grad = gloss / N * sum of tiles, each component summed in
+// the same fixed order.
+__global__ __launch_bounds__(kFinalizeThreads) void k_adj_finalize(AdjArgs a, int32_t phase)
 {
     const int32_t k = blockIdx.x;
-    const int lane = threadIdx.x & 63;
+    const int tid = threadIdx.x;
     if (phase == 0) {
         double o[2];
         finalize_set(a.loss_part + 2 * (int64_t)k * a.tiles, a.tiles, a.n, (double)a.W * a.dt, o);
-        if (lane == 0)
+        if (tid == 0)
             a.loss[k] = o[0];
         return;
     }
+    __shared__ double red[kGrad][kFinalizeThreads / 64];
     const double *gp = a.grad_part + kGrad * (int64_t)k * a.tiles;
-    const double scale = a.gloss[k] / (double)a.n;
+    double acc[kGrad];
+#pragma unroll
+    for (int r = 0; r < kGrad; ++r)
+        acc[r] = 0.0;
+    for (int64_t t = tid; t < a.tiles; t += kFinalizeThreads) {
+#pragma unroll
+        for (int r = 0; r < kGrad; ++r)
+            acc[r] += gp[kGrad * t + r];
+    }
 #pragma unroll
     for (int r = 0; r < kGrad; ++r) {
-        double acc = 0.0;
-        for (int64_t t = lane; t < a.tiles; t += 64)
-            acc += gp[kGrad * t + r];
-        acc = wave_sum(acc);
-        if (lane == 0)
-            a.grad[kGrad * (int64_t)k + r] = acc * scale;
+        acc[r] = wave_sum(acc[r]);
+        if ((tid & 63) == 0)
+            red[r][tid >> 6] = acc[r];
+    }
+    __syncthreads();
+    if (tid < kGrad) {
+        double s = red[tid][0];
+#pragma unroll
+        for (int w = 1; w < kFinalizeThreads / 64; ++w)
+            s += red[tid][w];
+        a.grad[kGrad * (int64_t)k + tid] = s * (a.gloss[k] / (double)a.n);
     }
 }
 
@@ -813,8 +829,9 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         else
             hipLaunchKernelGGL(k_adj_forward<0>, dim3(grid), dim3(256), 0, st, a);
     } else {
-        // B = 16 (Euler-Maruyama default) stages in ~350 VGPRs: one wavefront per SIMD. B = 8
-        // fits two (Euler-Maruyama on request; always for Heun, whose stage is larger).
+        // B = 16 is the default for both schemes: one wavefront per SIMD. B = 8 (on request) fits
+        // two Euler-Maruyama wavefronts per SIMD; the Heun backward runs one wavefront per SIMD at
+        // either staging length.
         const int B = cfg->stage_steps == 8 ? 8 : 16;
         const int blocks_per_cu = (!heun && B == 8) ? 2 : 1;
         // level-1 noise in LDS when every resident block's copy fits (and one block's share is
@@ -857,6 +874,7 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
     }
     if (hipGetLastError() != hipSuccess)
         return ABP_E_HIP;
-    hipLaunchKernelGGL(k_adj_finalize, dim3((unsigned)n_sets), dim3(64), 0, st, a, phase);
+    hipLaunchKernelGGL(k_adj_finalize, dim3((unsigned)n_sets), dim3(kFinalizeThreads), 0, st, a,
+                       phase);
     return launch_status();
 }

@@ -106,17 +106,20 @@ __global__ __launch_bounds__(256) void k_batched(BatchArgs a)
     }
 }
 
-// One wavefront per set.
-__global__ __launch_bounds__(64) void k_batched_finalize(const SetRow *rows, const double *part,
-                                                         const uint32_t *hist32, int32_t n_bins,
-                                                         double dt, double *out, uint64_t *hist64)
+// One block of kFinalizeThreads per set.
+__global__ __launch_bounds__(kFinalizeThreads) void k_batched_finalize(const SetRow *rows,
+                                                                       const double *part,
+                                                                       const uint32_t *hist32,
+                                                                       int32_t n_bins, double dt,
+                                                                       double *out,
+                                                                       uint64_t *hist64)
 {
     const uint32_t k = blockIdx.x;
     const SetRow &row = rows[k];
     const double wtime = (double)(row.n_steps - row.win_begin) * dt;
     finalize_set(part + 2 * row.first_tile, (row.n_traj + 63) / 64, row.n_traj, wtime,
                  out + 2 * (size_t)k);
-    for (int b = threadIdx.x; b < n_bins; b += 64)
+    for (int b = threadIdx.x; b < n_bins; b += kFinalizeThreads)
         hist64[(size_t)k * n_bins + b] = hist32[(size_t)k * n_bins + b];
 }
 
@@ -261,7 +264,7 @@ extern "C" abp_status abp_integrate_batched(int32_t n_sets, const abp_params *h_
         dispatch_batched<1>(a, sh, (int)grid, st);
     if (hipGetLastError() != hipSuccess)
         return ABP_E_HIP;
-    hipLaunchKernelGGL(k_batched_finalize, dim3((unsigned)n_sets), dim3(64), 0, st, a.rows, a.part,
+    hipLaunchKernelGGL(k_batched_finalize, dim3((unsigned)n_sets), dim3(kFinalizeThreads), 0, st, a.rows, a.part,
                        a.hist, cfg->n_bins, cfg->dt, d_out, d_hist);
     if (hipGetLastError() != hipSuccess)
         return ABP_E_HIP;

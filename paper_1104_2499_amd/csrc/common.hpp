@@ -51,13 +51,17 @@ inline bool bins_ok(int32_t n_bins)
 // The library runs on gfx950 only; the answer is cached per device ordinal.
 abp_status check_device();
 
+// FP64 parameters -> FP32 wavefront constants. The phase enters only through cos/sin in
+// revolutions (period 1), so it is reduced to [0, 1) in FP64 first: the kernels then add it to
+// positions of magnitude <= 1/2 without losing low bits, and stay inside the hardware cosine's
+// argument range for any finite phase. Phases already in [0, 1) are unchanged.
 inline Coef make_coef(const abp_params &p, double dt)
 {
     Coef k;
     k.dt = (float)dt;
     k.half_dt = (float)(0.5 * dt);
     k.bm = (float)(-2.0 * 0.69314718055994530942 * (2.0 * p.D * dt));
-    k.phi = (float)p.phi;
+    k.phi = (float)(p.phi - std::floor(p.phi));
     k.K1 = (float)(2.0 * kPi * p.U0);
     k.B = (float)(8.0 * kPi * p.U0 * p.a);
     k.FH = (float)(p.F0 + 4.0 * kPi * p.U0 * p.a);
@@ -132,8 +136,8 @@ inline abp_status launch_status()
     return hipGetLastError() == hipSuccess ? ABP_OK : ABP_E_HIP;
 }
 
-inline int64_t n_tiles(int64_t n) { return (n + 63) / 64; }
+constexpr int64_t n_tiles(int64_t n) { return (n + 63) / 64; }
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace abp

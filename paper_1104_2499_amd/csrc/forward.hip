@@ -4,9 +4,10 @@
 // Layout of the reduction workspace (abp_reduce_workspace_bytes):
 //   double part[n_tiles][2]   sums of delta and delta^2 over each 64-particle tile, delta = window
 //                             displacement in FP64; tile t = particles [64 t, 64 t + 64)
-//   uint32 hist[n_bins]       counts of x mod 1 (integer atomics: order-free, hence deterministic)
-// The optional time-accumulated histogram goes to a caller-owned u64 array instead: each block
-// counts into LDS and adds its counts once at the end.
+//   uint32 hist[n_bins]       counts of x mod 1 (integer atomics: order-free, hence deterministic);
+//                             each block counts into LDS and adds its nonzero bins once at the end
+// The optional time-accumulated histogram goes to a caller-owned u64 array instead, LDS-privatised
+// in the same way.
 // Tiles do not depend on the launch shape, and abp_reduce adds them in a fixed order, so the
 // results are bit-identical for every tuning.
 #include "reduce.hpp"
@@ -63,7 +64,7 @@ struct FwdArgs {
     int32_t acc_bins;
 };
 
-inline size_t hist_offset(int64_t n)
+constexpr size_t hist_offset(int64_t n)
 {
     return align_up((size_t)n_tiles(n) * 2 * sizeof(double), 256);
 }
@@ -90,21 +91,26 @@ __device__ __forceinline__ void advance_counted(const FwdArgs &a, const uint32_t
     advance<SCHEME, PPL, UNROLL>(a.k, a.s, pid, p, step, stop);
 }
 
+// Dynamic LDS of k_integrate: [acc_bins] u32 for the time-accumulated histogram (COUNTED), then
+// [n_bins] u32 for the final-position histogram of a reducing call.
 template <int SCHEME, int PPL, int UNROLL, bool COUNTED>
 __global__ __launch_bounds__(256) void k_integrate(FwdArgs a)
 {
-    extern __shared__ uint32_t loc[];  // [acc_bins] when COUNTED
+    extern __shared__ uint32_t lds[];
+    uint32_t *loc = lds;                                  // [acc_bins] when COUNTED
+    uint32_t *hloc = lds + (COUNTED ? a.acc_bins : 0);    // [n_bins] when reducing
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t base = wave * 64 * PPL;
     const int64_t n = a.st.n;
-    if (base >= n && !COUNTED)
-        return;  // wavefront-uniform; with COUNTED every wave reaches the block barriers
-    if constexpr (COUNTED) {
-        for (int b = threadIdx.x; b < a.acc_bins; b += blockDim.x)
-            loc[b] = 0u;
-        __syncthreads();
-    }
+    const bool hist = a.part && a.n_bins > 0;  // block-uniform
+    // wavefront-uniform; with a block-level histogram every wave reaches the block barriers
+    if (base >= n && !COUNTED && !hist)
+        return;
+    if constexpr (COUNTED)
+        clear_hist(loc, a.acc_bins);
+    if (hist)
+        clear_hist(hloc, a.n_bins);
 
     if (base < n) {
         Particle p[PPL];
@@ -152,7 +158,7 @@ __global__ __launch_bounds__(256) void k_integrate(FwdArgs a)
                 if (!snap_here)
                     xs[q] = live[q] ? a.snap.x64(base + 64 * q + lane) : 0.0;
             }
-            reduce_tiles<PPL>(xe, xs, live, base / 64, n, lane, a.n_bins, a.part, a.hist);
+            reduce_tiles<PPL>(xe, xs, live, base / 64, n, lane, a.n_bins, a.part, hloc);
         }
     }
 
@@ -163,32 +169,42 @@ __global__ __launch_bounds__(256) void k_integrate(FwdArgs a)
                 atomicAdd(reinterpret_cast<unsigned long long *>(&a.acc[b]),
                           (unsigned long long)loc[b]);
     }
+    if (hist)
+        flush_hist(hloc, a.hist, a.n_bins);
 }
 
-// Reduction from two stored states (window start, window end); one particle per lane.
+// Reduction from two stored states (window start, window end); one particle per lane, the
+// histogram counted per block in LDS ([n_bins] u32 of dynamic LDS).
 __global__ __launch_bounds__(256) void k_reduce_state(StateView snap, StateView end,
                                                       int32_t n_bins, double *part, uint32_t *hist)
 {
+    extern __shared__ uint32_t hloc[];
     const int lane = threadIdx.x & 63;
     const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64;
     const int64_t n = end.n;
-    if (base >= n)
-        return;
-    const int64_t i = base + lane;
-    bool live[1] = {i < n};
-    double xe[1] = {live[0] ? end.x64(i) : 0.0};
-    double xs[1] = {live[0] ? snap.x64(i) : 0.0};
-    reduce_tiles<1>(xe, xs, live, base / 64, n, lane, n_bins, part, hist);
+    if (n_bins > 0)
+        clear_hist(hloc, n_bins);
+    if (base < n) {
+        const int64_t i = base + lane;
+        bool live[1] = {i < n};
+        double xe[1] = {live[0] ? end.x64(i) : 0.0};
+        double xs[1] = {live[0] ? snap.x64(i) : 0.0};
+        reduce_tiles<1>(xe, xs, live, base / 64, n, lane, n_bins, part, hloc);
+    }
+    if (n_bins > 0)
+        flush_hist(hloc, hist, n_bins);
 }
 
-// Fixed-order FP64 combine of the tile partials by one wavefront (the same routine finishes each
-// set of a batched sweep, so a set run alone and inside a sweep agree bit for bit).
-__global__ __launch_bounds__(64) void k_finalize(const double *part, int64_t ntiles,
-                                                 const uint32_t *hist32, int32_t n_bins, int64_t n,
-                                                 double window_time, double *out, uint64_t *hist64)
+// Fixed-order FP64 combine of the tile partials by one block of kFinalizeThreads (the same routine
+// finishes each set of a batched sweep, so a set run alone and inside a sweep agree bit for bit).
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize(const double *part, int64_t ntiles,
+                                                               const uint32_t *hist32,
+                                                               int32_t n_bins, int64_t n,
+                                                               double window_time, double *out,
+                                                               uint64_t *hist64)
 {
     finalize_set(part, ntiles, n, window_time, out);
-    for (int b = threadIdx.x; b < n_bins; b += 64)
+    for (int b = threadIdx.x; b < n_bins; b += kFinalizeThreads)
         hist64[b] = hist32[b];
 }
 
@@ -198,7 +214,8 @@ static void launch_integrate(const FwdArgs &a, int block, hipStream_t st)
     const int64_t waves = (a.st.n + 64 * PPL - 1) / (64 * PPL);
     const int64_t threads = waves * 64;
     const unsigned grid = (unsigned)((threads + block - 1) / block);
-    const size_t lds = COUNTED ? sizeof(uint32_t) * (size_t)a.acc_bins : 0;
+    const size_t lds = sizeof(uint32_t) * ((COUNTED ? (size_t)a.acc_bins : 0) +
+                                           (a.part ? (size_t)a.n_bins : 0));
     hipLaunchKernelGGL((k_integrate<SCHEME, PPL, UNROLL, COUNTED>), dim3(grid), dim3(block), lds,
                        st, a);
 }
@@ -254,9 +271,11 @@ static StateView view(const abp_state *s)
     return v;
 }
 
-extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const abp_state *s,
-                                    const abp_state *snap, void *d_ws, size_t ws_bytes,
-                                    int32_t n_bins, const abp_tuning *tune, void *stream)
+// Validates an integration call and fills its kernel arguments, except the reduction outputs
+// (a.part, a.hist), which the caller points at its workspace when `reduce` is set.
+static abp_status plan_integrate(const abp_params *p, const abp_run *r, const abp_state *s,
+                                 const abp_state *snap, bool reduce, int32_t n_bins,
+                                 const abp_tuning *tune, FwdArgs &a, Shape &sh)
 {
     if (!p || !r || !state_ok(s) || !params_ok(*p))
         return ABP_E_ARG;
@@ -273,22 +292,16 @@ extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const
         return ABP_E_ARG;
     const int64_t end = r->step0 + r->n_steps;
     const bool snap_write = r->win_begin >= r->step0 && r->win_begin <= end;
-    const bool reduce = d_ws != nullptr;
     if (reduce && (r->win_begin < 0 || r->win_begin > end))
         return ABP_E_ARG;  // a reduction needs a window that is open by the end of the call
     if ((snap_write || reduce) && (!state_ok(snap) || snap->n != s->n))
         return ABP_E_ARG;
-    if (reduce && (!bins_ok(n_bins) || !aligned(d_ws, 256)))
+    if (reduce && !bins_ok(n_bins))
         return ABP_E_ARG;
-    Shape sh;
     if (!resolve_tuning(tune, kDefaultForward, sh))
         return ABP_E_ARG;
-    if (reduce && ws_bytes < abp_reduce_workspace_bytes(s->n, n_bins))
-        return ABP_E_WORKSPACE;
-    if (abp_status st = check_device())
-        return st;
 
-    FwdArgs a{};
+    a = FwdArgs{};
     a.st = view(s);
     if (snap_write || reduce)
         a.snap = view(snap);
@@ -304,18 +317,42 @@ extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const
         a.acc = r->d_hist_acc;
         a.acc_bins = r->hist_bins;
     }
-    if (reduce) {
-        a.part = reinterpret_cast<double *>(d_ws);
-        a.hist = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(d_ws) + hist_offset(s->n));
-    }
-    hipStream_t st = as_stream(stream);
-    if (reduce)
-        zero_hist(a.hist, n_bins, st);
-    if (r->scheme == ABP_EM)
+    return ABP_OK;
+}
+
+// Enqueue the integration (and the zeroing of its histogram counts when it reduces).
+static abp_status enqueue_integrate(const FwdArgs &a, const Shape &sh, int32_t scheme,
+                                    hipStream_t st)
+{
+    if (a.part)
+        zero_hist(a.hist, a.n_bins, st);
+    if (scheme == ABP_EM)
         dispatch_integrate<0>(a, sh, st);
     else
         dispatch_integrate<1>(a, sh, st);
     return launch_status();
+}
+
+extern "C" abp_status abp_integrate(const abp_params *p, const abp_run *r, const abp_state *s,
+                                    const abp_state *snap, void *d_ws, size_t ws_bytes,
+                                    int32_t n_bins, const abp_tuning *tune, void *stream)
+{
+    const bool reduce = d_ws != nullptr;
+    FwdArgs a;
+    Shape sh;
+    if (abp_status st = plan_integrate(p, r, s, snap, reduce, n_bins, tune, a, sh))
+        return st;
+    if (reduce && !aligned(d_ws, 256))
+        return ABP_E_ARG;
+    if (reduce && ws_bytes < abp_reduce_workspace_bytes(s->n, n_bins))
+        return ABP_E_WORKSPACE;
+    if (abp_status st = check_device())
+        return st;
+    if (reduce) {
+        a.part = reinterpret_cast<double *>(d_ws);
+        a.hist = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(d_ws) + hist_offset(s->n));
+    }
+    return enqueue_integrate(a, sh, r->scheme, as_stream(stream));
 }
 
 extern "C" abp_status abp_reduce_state(const abp_state *snap, const abp_state *end,
@@ -334,24 +371,27 @@ extern "C" abp_status abp_reduce_state(const abp_state *snap, const abp_state *e
                                                   hist_offset(end->n));
     zero_hist(hist, n_bins, st);
     const unsigned grid = (unsigned)((n_tiles(end->n) * 64 + 255) / 256);
-    hipLaunchKernelGGL(k_reduce_state, dim3(grid), dim3(256), 0, st, view(snap), view(end), n_bins,
-                       part, hist);
+    hipLaunchKernelGGL(k_reduce_state, dim3(grid), dim3(256), sizeof(uint32_t) * (size_t)n_bins, st,
+                       view(snap), view(end), n_bins, part, hist);
     return launch_status();
 }
 
-extern "C" abp_status abp_reduce(const void *d_ws, int64_t n, int32_t n_bins, double window_time,
-                                 double *d_out, uint64_t *d_hist, void *stream)
+extern "C" abp_status abp_reduce(const void *d_ws, size_t ws_bytes, int64_t n, int32_t n_bins,
+                                 double window_time, double *d_out, uint64_t *d_hist,
+                                 void *stream)
 {
     if (!d_ws || !aligned(d_ws, 256) || n < 1 || n > kMaxParticles || !bins_ok(n_bins) ||
         !(window_time > 0.0) || !is_finite(window_time) || !d_out || !aligned(d_out, 8) ||
         (n_bins > 0 && (!d_hist || !aligned(d_hist, 8))))
         return ABP_E_ARG;
+    if (ws_bytes < abp_reduce_workspace_bytes(n, n_bins))
+        return ABP_E_WORKSPACE;
     if (abp_status st = check_device())
         return st;
     const double *part = reinterpret_cast<const double *>(d_ws);
     const uint32_t *hist = reinterpret_cast<const uint32_t *>(
         reinterpret_cast<const char *>(d_ws) + hist_offset(n));
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, as_stream(stream), part, n_tiles(n),
-                       hist, n_bins, n, window_time, d_out, d_hist);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), 0, as_stream(stream), part,
+                       n_tiles(n), hist, n_bins, n, window_time, d_out, d_hist);
     return launch_status();
 }

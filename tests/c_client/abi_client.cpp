@@ -89,7 +89,7 @@ int main(int argc, char **argv)
 
     ABP_OK_OR_EXIT(abp_init_state(&s, seed, 0, nullptr));
     ABP_OK_OR_EXIT(abp_integrate(&p, &r, &s, &snap, d_ws, ws_bytes, bins, nullptr, nullptr));
-    ABP_OK_OR_EXIT(abp_reduce(d_ws, n, bins, (double)window * dt, d_out, d_hist, nullptr));
+    ABP_OK_OR_EXIT(abp_reduce(d_ws, ws_bytes, n, bins, (double)window * dt, d_out, d_hist, nullptr));
 
     double out[2];
     uint64_t hist[bins];

@@ -27,7 +27,7 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.abp_abi_version() == 1
+    assert lib.abp_abi_version() == 2
     for s in range(5):
         assert lib.abp_status_str(s)
     assert lib.abp_status_str(99) == b"unknown status"
@@ -135,9 +135,13 @@ def test_other_entry_points_validate(lib):
     assert lib.abp_philox(0, 0x1000, 0x1000, 0x1000, None) == E_ARG
     assert lib.abp_philox(4, None, 0x1000, 0x1000, None) == E_ARG
     assert lib.abp_init_state(None, 1, 0, None) == E_ARG
-    assert lib.abp_reduce(None, 10, 256, 1.0, 0x1000, 0x1000, None) == E_ARG
-    assert lib.abp_reduce(0x10000, 10, 256, 0.0, 0x1000, 0x1000, None) == E_ARG
-    assert lib.abp_reduce(0x10000, 10, 256, 1.0, 0x1000, None, None) == E_ARG
+    assert lib.abp_reduce(None, 1 << 20, 10, 256, 1.0, 0x1000, 0x1000, None) == E_ARG
+    assert lib.abp_reduce(0x10000, 1 << 20, 10, 256, 0.0, 0x1000, 0x1000, None) == E_ARG
+    assert lib.abp_reduce(0x10000, 1 << 20, 10, 256, 1.0, 0x1000, None, None) == E_ARG
+    # a workspace shorter than the query for (n, n_bins) is refused before any device access
+    need = lib.abp_reduce_workspace_bytes(1 << 20, 256)
+    assert lib.abp_reduce(0x10000, need - 1, 1 << 20, 256, 1.0, 0x1000, 0x1000,
+                          None) == _lib.ABP_E_WORKSPACE
     a, b = _state(), _state(n=32)
     assert lib.abp_reduce_state(ctypes.byref(a), ctypes.byref(b), 256, 0x10000, 1 << 20,
                                 None) == E_ARG

@@ -127,11 +127,12 @@ def test_batched_adjoint_sets_match_oracle(gpu, orc):
 
 
 def test_full_horizon_per_particle_gradients(gpu, orc):
-    """G3 at the 65536-particle, 1e4-step, W = 2000, K = 100 configuration, on 2048 sampled
+    """G3 at the 65536-particle, 1e4-step, W = 2000, K = 100 configuration, on 8192 sampled
     particles: (i) per particle and component, the GPU-oracle gradient difference is within twice
     the oracle's own change under FP32-sized path perturbations (2^-24 model), for >= 99% of the
-    pairs; (ii) summed over the particles whose FP64 gradient is well-conditioned (changes < 1e-3
-    under that perturbation), the GPU gradient matches within 1e-3 relative."""
+    pairs; (ii) summed over the particles whose FP64 gradient is well-conditioned (every component
+    changes by < 1e-4 relative under that perturbation; about 7% of the particles at this
+    horizon), the GPU gradient matches within 1e-3 relative."""
     from paper_1104_2499_amd import adjoint, api
 
     theta = _theta(1)
@@ -143,7 +144,7 @@ def test_full_horizon_per_particle_gradients(gpu, orc):
     g, gp = adjoint.backward(rows, cfg, ws, torch.ones(1, dtype=torch.float64), per_particle=True)
     run = api.run(_params(theta[0]), n=n, steps=S, window=W, scheme="em", seed=42, bins=0)
     assert float(loss[0].cpu()) == run.mean_v
-    ids = np.arange(0, n, 32, dtype=np.uint64)  # 2048 sampled particles
+    ids = np.arange(0, n, 8, dtype=np.uint64)  # 8192 sampled particles
     x0, v0, e0 = orc.init_state(ids.size, 42, ids=ids)
     p = _params(theta[0])
     _, g_ora = orc.adjoint(p, x0, v0, e0, S, W, seed=42, ids=ids)
@@ -154,12 +155,12 @@ def test_full_horizon_per_particle_gradients(gpu, orc):
     d_own = np.abs(g_eps - g_ora)
     within = d_gpu <= 2 * d_own + 1e-6 * scale
     floor = np.maximum(np.abs(g_ora), 1e-6 * scale)
-    C = (d_own / floor < 1e-3).all(axis=1)
+    C = (d_own / floor < 1e-4).all(axis=1)
     print(f"pairs within 2x own sensitivity: {within.mean():.4f}; well-conditioned particles "
           f"{C.mean():.3f}; median |gpu-ora|/|ora| {np.median(d_gpu / floor):.2e}, "
           f"median own {np.median(d_own / floor):.2e}")
     assert within.mean() >= 0.99
-    assert C.sum() >= 100
+    assert C.sum() >= 300
     np.testing.assert_allclose(gpp[C].sum(axis=0), g_ora[C].sum(axis=0), rtol=1e-3,
                                atol=1e-6 * np.abs(g_ora[C].sum(axis=0)).max())
 

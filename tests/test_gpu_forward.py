@@ -251,7 +251,18 @@ def test_ensemble_parity_1e4_steps(gpu, orc, scheme):
     edge = np.minimum(np.abs(frac * 256 - np.round(frac * 256)), 1.0) / 256
     agree = (np.abs(xg - x) < 1e-6) & (edge > 1e-6)
     assert np.array_equal(bg[agree], bo[agree])
-    assert np.abs(hg - hist.astype(np.int64)).sum() <= 2 * (bg != bo).sum()
+    # where trajectories do not agree, the bins move no more than the oracle's own under 2^-24
+    # rounding perturbations: the count of particles in a different bin, and the L1 distance of
+    # the histograms, are within twice the oracle's self-divergence (plus a few particles)
+    bp = np.minimum(np.floor((xp - np.floor(xp)) * 256), 255).astype(np.int64)
+    hp = np.bincount(bp, minlength=256)
+    ho = hist.astype(np.int64)
+    moved, moved_own = int((bg != bo).sum()), int((bp != bo).sum())
+    l1, l1_own = int(np.abs(hg - ho).sum()), int(np.abs(hp - ho).sum())
+    print(f"{scheme} 1e4 histogram: particles in another bin {moved} (oracle self {moved_own}), "
+          f"L1 {l1} (oracle self {l1_own})")
+    assert moved <= 2 * moved_own + 4
+    assert l1 <= 2 * l1_own + 8
 
 
 @pytest.mark.parametrize("scheme,order", [("em", 1), ("heun", 2)])
@@ -297,6 +308,25 @@ def test_other_parameters(gpu, orc, params):
     err = mixed_err(_gpu_xve(res), (x, v, e))
     assert (err <= 1e-4).mean() >= 0.999 and err.max() <= 1e-3
     assert abs(res.mean_v - mean) <= 1e-5
+
+
+@pytest.mark.parametrize("phi", [0.1903 + 1000.0, -0.1903 - 517.0, 0.1903 - 1.0])
+def test_large_and_negative_phase(gpu, orc, phi):
+    """The potential is periodic in its phase: a phase far outside [0, 1), or negative, gives the
+    trajectories of its reduction to [0, 1) (the FP64 oracle evaluates the phase as given)."""
+    params = dict(BASE, phi=phi, U0=0.7, a=0.4)
+    for scheme in ("em", "heun"):
+        res, (x, v, e, xs), (mean, se, hist) = _run_pair(orc, params, 2048, 1000, scheme, seed=13)
+        err = mixed_err(_gpu_xve(res), (x, v, e))
+        assert (err <= 1e-4).mean() >= 0.999 and err.max() <= 1e-3, (scheme, err.max())
+        assert abs(res.mean_v - mean) <= 1e-5
+    # the library reduces the phase before it reaches FP32: the same bits as the reduced phase
+    from paper_1104_2499_amd import api
+
+    red = dict(params, phi=phi - np.floor(phi))
+    a = api.run(params, n=2048, steps=1000, scheme="heun", seed=13, bins=0)
+    b = api.run(red, n=2048, steps=1000, scheme="heun", seed=13, bins=0)
+    assert torch.equal(a.state.xf, b.state.xf) and torch.equal(a.state.lo, b.state.lo)
 
 
 @pytest.mark.parametrize("scheme", ["em", "heun"])
