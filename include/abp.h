@@ -166,6 +166,25 @@ abp_status abp_reduce_state(const abp_state *snap, const abp_state *end, int32_t
                             void *d_ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
+ * Allocation-free form of abp_integrate + abp_reduce, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * ------------------------------------------------------------------------------------------- */
+#define ABP_NOALLOC_MAX_PARTICLES (1 << 24)
+
+/* Writes exactly what abp_integrate(p, r, s, snap, ws, .., n_bins, tune) followed by
+ * abp_reduce(ws, .., s->n, n_bins, window_time, d_out, d_hist) write (the state, the snapshot,
+ * d_out[2], d_hist[n_bins]), bit for bit, but keeps the reduction partials in a fixed device
+ * array of the library (4 MiB + 16 KiB per GPU, held until the process ends) instead of a caller
+ * workspace. It calls no allocator. Requires a window (0 <= win_begin <= step0 + n_steps);
+ * s->n > ABP_NOALLOC_MAX_PARTICLES returns ABP_E_WORKSPACE. Every call on a GPU shares that
+ * GPU's array and clears what must start at zero: calls in order on one stream are safe, calls
+ * that overlap in time on one GPU (different streams or host threads) race. */
+abp_status abp_integrate_reduce_noalloc(const abp_params *p, const abp_run *r,
+                                        const abp_state *s, const abp_state *snap,
+                                        int32_t n_bins, double window_time, double *d_out,
+                                        uint64_t *d_hist, const abp_tuning *tune, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
  * Batched sweep: many parameter sets, each an ensemble of its own size and step count, in one
  * persistent launch (Sec. 2 runs one work item per parameter set concurrently).
  * ------------------------------------------------------------------------------------------- */

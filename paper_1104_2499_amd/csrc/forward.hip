@@ -10,6 +10,8 @@
 // in the same way.
 // Tiles do not depend on the launch shape, and abp_reduce adds them in a fixed order, so the
 // results are bit-identical for every tuning.
+#include <mutex>
+
 #include "reduce.hpp"
 
 namespace abp {
@@ -393,5 +395,73 @@ extern "C" abp_status abp_reduce(const void *d_ws, size_t ws_bytes, int64_t n, i
         reinterpret_cast<const char *>(d_ws) + hist_offset(n));
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), 0, as_stream(stream), part,
                        n_tiles(n), hist, n_bins, n, window_time, d_out, d_hist);
+    return launch_status();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free variant of abp_integrate + abp_reduce, for callers that cannot allocate device
+// memory. The reduction workspace is a file-scope device array (one copy per GPU, held until the
+// process ends), sized for kNoAllocMaxParticles particles and kMaxBins bins. Host code never
+// passes the array's name to a kernel: it looks up the array's device address once per device
+// (hipGetSymbolAddress, with that device current) and passes that pointer.
+// ---------------------------------------------------------------------------------------------
+namespace abp {
+
+constexpr int64_t kNoAllocMaxParticles = ABP_NOALLOC_MAX_PARTICLES;
+constexpr size_t kNoAllocScratchBytes =
+    hist_offset(kNoAllocMaxParticles) + align_up((size_t)kMaxBins * sizeof(uint32_t), 256);
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch array, looked up on the first call per device.
+static abp_status scratch_pointer(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return ABP_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return ABP_E_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ABP_OK;
+}
+
+}  // namespace abp
+
+extern "C" abp_status abp_integrate_reduce_noalloc(const abp_params *p, const abp_run *r,
+                                                   const abp_state *s, const abp_state *snap,
+                                                   int32_t n_bins, double window_time,
+                                                   double *d_out, uint64_t *d_hist,
+                                                   const abp_tuning *tune, void *stream)
+{
+    FwdArgs a;
+    Shape sh;
+    if (abp_status st = plan_integrate(p, r, s, snap, true, n_bins, tune, a, sh))
+        return st;
+    if (!(window_time > 0.0) || !is_finite(window_time) || !d_out || !aligned(d_out, 8) ||
+        (n_bins > 0 && (!d_hist || !aligned(d_hist, 8))))
+        return ABP_E_ARG;
+    if (s->n > kNoAllocMaxParticles)
+        return ABP_E_WORKSPACE;
+    if (abp_status st = check_device())
+        return st;
+    void *ws = nullptr;
+    if (abp_status st = scratch_pointer(&ws))
+        return st;
+    a.part = reinterpret_cast<double *>(ws);
+    a.hist = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(ws) + hist_offset(s->n));
+    hipStream_t st = as_stream(stream);
+    if (abp_status e = enqueue_integrate(a, sh, r->scheme, st))
+        return e;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinalizeThreads), 0, st, a.part, n_tiles(s->n),
+                       a.hist, n_bins, s->n, window_time, d_out, d_hist);
     return launch_status();
 }

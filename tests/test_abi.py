@@ -256,3 +256,33 @@ def test_ctypes_signatures_match_the_c_prototypes():
             else:
                 ctype = a.replace("const ", "").rsplit(" ", 1)[0].strip()
                 assert t is scalar[ctype], (name, a)
+
+
+def test_noalloc_entry_point_validates(lib):
+    """The allocation-free integrate + reduce checks its arguments like abp_integrate, refuses
+    ensembles larger than its fixed scratch with ABP_E_WORKSPACE, and reports a missing gfx950
+    device, all before anything is enqueued."""
+    import torch
+
+    from paper_1104_2499_amd import _lib
+    from paper_1104_2499_amd.api import make_params
+
+    p = make_params()
+    win = _lib.AbpRun(1e-3, 100, 0, 50, 42, 0, 0)
+
+    def call(r=win, n=64, bins=256, wt=0.05, out=0x1000, hist=0x2000):
+        s, snap = _state(n=n), _state(n=n)
+        return lib.abp_integrate_reduce_noalloc(ctypes.byref(p), ctypes.byref(r),
+                                                ctypes.byref(s), ctypes.byref(snap), bins, wt,
+                                                out, hist, None, None)
+
+    assert call(r=_lib.AbpRun(1e-3, 100, 0, -1, 42, 0, 0)) == _lib.ABP_E_ARG  # no window
+    assert call(bins=100) == _lib.ABP_E_ARG
+    assert call(wt=0.0) == _lib.ABP_E_ARG
+    assert call(out=None) == _lib.ABP_E_ARG
+    assert call(out=0x1004) == _lib.ABP_E_ARG
+    assert call(hist=None) == _lib.ABP_E_ARG
+    assert call(hist=None, bins=0) != _lib.ABP_E_ARG
+    assert call(n=_lib.NOALLOC_MAX_PARTICLES + 1) == _lib.ABP_E_WORKSPACE
+    if not torch.cuda.is_available():
+        assert call(n=_lib.NOALLOC_MAX_PARTICLES) == _lib.ABP_E_DEVICE
