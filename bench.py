@@ -314,16 +314,22 @@ def sweep_bench(reps: int = 2, tune_batched=None, tune_single=None) -> dict:
     work = float((n_traj.astype(np.int64) * n_steps).sum())
     # lanes past a set's last trajectory in its last 64-particle tile still step (masked)
     lanes = float(((n_traj.astype(np.int64) + 63) // 64 * 64 * n_steps).sum())
-    ws = api.batched_workspace(n_traj, wl["bins"])
-    api.sweep(table, n_traj, n_steps, scheme=wl["scheme"], seed=wl["seed"], bins=wl["bins"], ws=ws,
-              tune=tune_batched)
+    # tables resident on the device before the timed region; each timed sweep plans its work
+    # list on the device, integrates and finalises
+    buf = api.SweepBuffers.make(table, n_traj, n_steps, bins=wl["bins"])
+
+    def one_sweep():
+        api.sweep_enqueue(buf, wl["dt"], wl["scheme"], wl["seed"], wl["bins"], tune_batched)
+    one_sweep()
+    api.check_device_status(buf.status, "sweep")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        r = api.sweep(table, n_traj, n_steps, scheme=wl["scheme"], seed=wl["seed"],
-                      bins=wl["bins"], ws=ws, tune=tune_batched)
+        one_sweep()
     torch.cuda.synchronize()
     t_sweep = (time.perf_counter() - t0) / reps
+    api.check_device_status(buf.status, "sweep")
+    mean_v = buf.out[:, 0].cpu().numpy()
 
     n, S = 1 << 20, 20_000
     state, snap = api.State.empty(n), api.State.empty(n)
@@ -347,7 +353,7 @@ def sweep_bench(reps: int = 2, tune_batched=None, tune_single=None) -> dict:
             "single_set_value": v_single, "single_set_config": f"{n} particles x {S} steps",
             "ratio_to_single_set": v_sweep / v_single,
             "masked_lane_fraction": 1.0 - work / lanes,
-            "finite_sets": int(np.isfinite(r.mean_v).sum())}
+            "finite_sets": int(np.isfinite(mean_v).sum())}
 
 
 def adjoint_bench(reps: int = 10, scheme: str = "em", ckpt: int | None = None) -> dict:
@@ -391,9 +397,14 @@ def adjoint_bench(reps: int = 10, scheme: str = "em", ckpt: int | None = None) -
 
     # five interleaved trials of each; medians (the one-wavefront-per-SIMD plain forward varies by
     # a few percent from run to run)
-    trials = [(timed(plain), timed(lambda: adjoint.forward(rows, cfg, ws)),
-               timed(lambda: adjoint.backward(rows, cfg, ws, gloss))) for _ in range(5)]
+    status = torch.empty(1, dtype=torch.int32, device="cuda")
+    trials = [(timed(plain),
+               timed(lambda: adjoint.forward(rows, cfg, ws, status=status, check_status=False)),
+               timed(lambda: adjoint.backward(rows, cfg, ws, gloss, status=status,
+                                              check_status=False)))
+              for _ in range(5)]
     t_plain, t_fwd, t_bwd = (float(np.median([t[i] for t in trials])) for i in range(3))
+    api.check_device_status(status, "adjoint")
     loss = float(adjoint.forward(rows, cfg, ws)[0].cpu())
     mean_v = float(plain()[0].cpu())
     return {"workload": "adjoint-64k", "scheme": scheme, "ckpt": K,
@@ -424,16 +435,19 @@ def adjoint_batched_bench(stage: int, ckpt: int, reps: int = 3) -> dict:
     gloss = torch.ones(wl["n_sets"], dtype=torch.float64, device="cuda")
     adjoint.forward(rows, cfg, ws)
     adjoint.backward(rows, cfg, ws, gloss)
+    status = torch.empty(1, dtype=torch.int32, device="cuda")
     times = []
     for _ in range(reps):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev[0].record()
-        adjoint.forward(rows, cfg, ws)
+        adjoint.forward(rows, cfg, ws, status=status, check_status=False)
         ev[1].record()
-        adjoint.backward(rows, cfg, ws, gloss)
+        adjoint.backward(rows, cfg, ws, gloss, status=status, check_status=False)
         ev[2].record()
         ev[2].synchronize()
         times.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
+    from paper_1104_2499_amd import api
+    api.check_device_status(status, "adjoint")
     nbytes = int(ws.numel())
     del ws
     torch.cuda.empty_cache()

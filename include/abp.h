@@ -26,14 +26,15 @@
  *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the null stream). The
  *    status is returned synchronously: arguments are validated before anything is enqueued, and
  *    on ABP_E_ARG / ABP_E_WORKSPACE / ABP_E_DEVICE nothing is written. ABP_E_HIP reports a
- *    launch or copy error from the HIP runtime.
+ *    launch error from the HIP runtime. Values that live in device tables (the batched sweep's
+ *    and the adjoint's parameter tables) are checked on the device instead: the result is
+ *    written to a device status word (d_status), and the outputs become NaN (see each call).
  *  - Results are deterministic: identical inputs give bit-identical outputs for every tuning and
  *    every repeat (FP64 partials are combined in a fixed order; histograms are integer counts).
  *  - Only gfx950 devices are accepted (ABP_E_DEVICE otherwise).
- *  - abp_init_state, abp_philox, abp_integrate, abp_reduce and abp_reduce_state only enqueue
- *    kernels (no host synchronisation, no memset), so they may be captured into a HIP graph once
- *    the first call on the device has run. abp_integrate_batched and abp_adjoint stage host
- *    tables and wait for them: they cannot be captured.
+ *  - Every entry point only enqueues kernels (no host synchronisation, no copies, no memset),
+ *    so any sequence of calls may be captured into a HIP graph once the first call on the
+ *    device has run (that call caches the device check).
  */
 #ifndef ABP_H
 #define ABP_H
@@ -45,7 +46,7 @@
 extern "C" {
 #endif
 
-#define ABP_ABI_VERSION 2
+#define ABP_ABI_VERSION 3
 
 typedef enum abp_status {
     ABP_OK = 0,
@@ -119,9 +120,10 @@ typedef struct abp_tuning {
 int abp_abi_version(void);
 const char *abp_status_str(abp_status s);
 
-/* Initial condition of an ensemble (the paper's work items start from a state the text does not
- * fix, Sec. 2; here x0 ~ U[0,1) on the 24-bit grid, v0 = e0 = 0) for particles id0..id0+n-1 of
- * set `set_id` under `seed` (see the noise contract). Writes all of *s (low parts zeroed). */
+/* Initial condition of an ensemble: the state (x, v, e) of Eqs. (1)-(2) at t = 0 for every work
+ * item of Fig. 1 (the paper does not fix it, Sec. 2; here x0 ~ U[0,1) on the 24-bit grid,
+ * v0 = e0 = 0) for particles id0..id0+n-1 of set `set_id` under `seed` (see the noise contract).
+ * Writes all of *s (low parts zeroed). */
 abp_status abp_init_state(const abp_state *s, uint64_t seed, uint32_t set_id, void *stream);
 
 /* Philox4x32-10 of m counters: d_ctr [m][4] u32, d_key [m][2] u32 -> d_out [m][4] u32. The
@@ -160,8 +162,10 @@ abp_status abp_integrate(const abp_params *p, const abp_run *r, const abp_state 
 abp_status abp_reduce(const void *d_ws, size_t ws_bytes, int64_t n, int32_t n_bins,
                       double window_time, double *d_out, uint64_t *d_hist, void *stream);
 
-/* The reduction stage alone (the ensemble averages of Sec. 2), from two states (window start and
- * end): writes the same partials into d_ws as abp_integrate does. */
+/* The reduction stage alone, from two states (window start and end): the ensemble averages of
+ * Sec. 2 (mean drift velocity of the ratchet current from the window displacement of x in
+ * Eq. (2), and the density of x over one period of the potential of Eq. (3)). Writes the same
+ * partials into d_ws as abp_integrate does; abp_reduce finishes them. */
 abp_status abp_reduce_state(const abp_state *snap, const abp_state *end, int32_t n_bins,
                             void *d_ws, size_t ws_bytes, void *stream);
 
@@ -195,28 +199,38 @@ typedef struct abp_batch {
     int32_t n_bins;   /* histogram bins per set: 0 or a power of two up to 4096 */
 } abp_batch;
 
-/* Bytes of workspace for abp_integrate_batched (0 if the sizes are invalid). */
-size_t abp_batched_workspace_bytes(int32_t n_sets, const int32_t *h_ntraj, int32_t n_bins);
+/* Bytes of workspace for abp_integrate_batched with n_sets sets (1 <= n_sets <= 2^20) whose tile
+ * counts ceil(n_traj[k] / 64) add up to n_tiles (or less: any upper bound of that sum will do,
+ * n_sets <= n_tiles < 2^31); 0 if the sizes are invalid. */
+size_t abp_batched_workspace_bytes(int32_t n_sets, int64_t n_tiles, int32_t n_bins);
 
-/* Integrate n_sets independent ensembles and reduce each one. Set k has parameters h_params[k],
- * h_ntraj[k] >= 1 particles (ids 0..h_ntraj[k]-1, Philox set id k) started from the workload
- * initial condition, h_nsteps[k] >= 1 steps, and a window of the last h_window[k] steps
- * (1 <= window <= steps; h_window NULL = h_nsteps[k] / 2). Outputs: d_out[2k], d_out[2k+1] =
- * mean drift velocity and its standard error; d_hist[k n_bins + b] = u64 histogram of the final
- * x mod 1. Each set's results equal, bit for bit, those of abp_init_state + abp_integrate +
- * abp_reduce run on that set alone with set_id = k, for every tuning. The host arrays are read
- * during the call; per-set constants and the work list are staged into d_ws, so the call returns
- * only after the stream has drained (it cannot be captured into a graph). tune: block, ppl,
- * unroll and waves_per_simd (grid = CUs x 4 x waves_per_simd waves); NULL = default. */
-abp_status abp_integrate_batched(int32_t n_sets, const abp_params *h_params,
-                                 const int32_t *h_ntraj, const int64_t *h_nsteps,
-                                 const int64_t *h_window, const abp_batch *cfg,
+/* Integrate n_sets independent ensembles and reduce each one, in one persistent launch. The tables
+ * are device arrays read on the device: set k has parameters d_params[k] (rows of ABP_N_PARAMS
+ * doubles), d_ntraj[k] >= 1 particles (ids 0..d_ntraj[k]-1, Philox set id k) started from the
+ * workload initial condition, d_nsteps[k] in [1, 2^34] steps, and a window of the last
+ * d_window[k] steps (1 <= window <= steps; d_window NULL = d_nsteps[k] / 2). Outputs:
+ * d_out[2k], d_out[2k+1] = mean drift velocity and its standard error; d_hist[k n_bins + b] =
+ * u64 histogram of the final x mod 1. Each set's results equal, bit for bit, those of
+ * abp_init_state + abp_integrate + abp_reduce run on that set alone with set_id = k, for every
+ * tuning. The work list (sets cut into tiles of 64 particles, longest step count first) is built
+ * on the device in d_ws. The host validates the scalars, pointers and the per-set part of the
+ * workspace; the device checks the tables: a set abp_integrate would reject is ABP_E_ARG, tiles
+ * beyond the workspace's capacity ABP_E_WORKSPACE. Then nothing is integrated, d_out is set to
+ * NaN and d_hist to zero. *d_status (a device int32; may be NULL) receives the device-side status
+ * (ABP_OK when the sweep ran). The call only enqueues. tune: block, ppl, unroll and
+ * waves_per_simd (grid = CUs x 4 x waves_per_simd waves); NULL = default. */
+abp_status abp_integrate_batched(int32_t n_sets, const abp_params *d_params,
+                                 const int32_t *d_ntraj, const int64_t *d_nsteps,
+                                 const int64_t *d_window, const abp_batch *cfg,
                                  const abp_tuning *tune, void *d_ws, size_t ws_bytes,
-                                 double *d_out, uint64_t *d_hist, void *stream);
+                                 double *d_out, uint64_t *d_hist, int32_t *d_status,
+                                 void *stream);
 
 /* ---------------------------------------------------------------------------------------------
- * Pathwise gradient of the window mean velocity (Euler-Maruyama or stochastic Heun), by a discrete
- * adjoint with checkpoints every ckpt_every steps and Philox noise regenerated in the backward pass.
+ * Pathwise gradient of the window mean velocity (the ratchet current of Sec. 2) with respect to
+ * the parameters of Eqs. (1)-(3), through the Euler-Maruyama or stochastic Heun map of the
+ * per-step loop of Fig. 1: a discrete adjoint with checkpoints every ckpt_every steps and Philox
+ * noise regenerated in the backward pass.
  * ------------------------------------------------------------------------------------------- */
 typedef struct abp_adjoint_cfg {
     double dt;           /* > 0 */
@@ -243,20 +257,23 @@ typedef struct abp_adjoint_cfg {
 size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set, int64_t n_steps,
                                    int64_t ckpt_every);
 
-/* phase 0 (forward): for each set k (parameters h_params[k], D > 0; n_per_set particles with ids
- * 0..n-1 from the workload initial condition) integrate S steps of cfg->scheme, store the
- * checkpoints in d_ws, and write d_loss[k] = L_k = (1/n) sum_i (x_S - x_{S-W}) / (W dt), the same
- * value abp_integrate + abp_reduce give for that set alone with set_id = k.
+/* phase 0 (forward): for each set k (parameters d_params[k], a device table of rows of
+ * ABP_N_PARAMS doubles; n_per_set particles with ids 0..n-1 from the workload initial condition)
+ * integrate S steps of cfg->scheme, store the checkpoints in d_ws, and write d_loss[k] = L_k =
+ * (1/n) sum_i (x_S - x_{S-W}) / (W dt), the same value abp_integrate + abp_reduce give for that
+ * set alone with set_id = k.
  * phase 1 (backward): with d_ws left by phase 0 for identical arguments, write
  * d_grad[8k + j] = d_gloss[k] * dL_k/dtheta_j, theta = (U0, a, D, d2, q, c, gamma0, F0), and,
  * if d_grad_particles is non-NULL, d_grad_particles[8 (k n + i) + j] = dJ_i/dtheta_j of particle
  * i of set k (unscaled; used for per-particle checks and gradient statistics).
- * h_params is read during the call (its per-set constants are staged into d_ws, after which the
- * call waits for the stream to drain); the kernels then run asynchronously on `stream`. */
-abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_params *h_params,
+ * The parameter table is checked on the device (each phase): a set abp_integrate would reject,
+ * or one with D <= 0, makes the device-side status ABP_E_ARG; then nothing is integrated and
+ * d_loss (phase 0) or d_grad (phase 1) is set to NaN. *d_status (a device int32; may be NULL)
+ * receives that status. The call only enqueues. */
+abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_params *d_params,
                        int64_t n_per_set, const abp_adjoint_cfg *cfg, void *d_ws, size_t ws_bytes,
                        double *d_loss, const double *d_gloss, double *d_grad,
-                       double *d_grad_particles, void *stream);
+                       double *d_grad_particles, int32_t *d_status, void *stream);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libabp.so")
 
 ABP_OK, ABP_E_ARG, ABP_E_HIP, ABP_E_WORKSPACE, ABP_E_DEVICE = range(5)
 ABP_EM, ABP_HEUN = 0, 1
+ABI_VERSION = 3
 NOALLOC_MAX_PARTICLES = 1 << 24
 STATUS_NAMES = {0: "ABP_OK", 1: "ABP_E_ARG", 2: "ABP_E_HIP", 3: "ABP_E_WORKSPACE",
                 4: "ABP_E_DEVICE"}
@@ -73,12 +74,12 @@ SIGNATURES = {
     "abp_integrate_reduce_noalloc": (ctypes.c_int, [_P(AbpParams), _P(AbpRun), _P(AbpState),
                                                     _P(AbpState), _i32, _f64, _vp, _vp,
                                                     _P(AbpTuning), _vp]),
-    "abp_batched_workspace_bytes": (_sz, [_i32, _vp, _i32]),
+    "abp_batched_workspace_bytes": (_sz, [_i32, _i64, _i32]),
     "abp_integrate_batched": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _P(AbpBatch),
-                                             _P(AbpTuning), _vp, _sz, _vp, _vp, _vp]),
+                                             _P(AbpTuning), _vp, _sz, _vp, _vp, _vp, _vp]),
     "abp_adjoint_workspace_bytes": (_sz, [_i32, _i64, _i64, _i64]),
     "abp_adjoint": (ctypes.c_int, [_i32, _i32, _vp, _i64, _P(AbpAdjointCfg), _vp, _sz, _vp, _vp,
-                                   _vp, _vp, _vp]),
+                                   _vp, _vp, _vp, _vp]),
 }
 
 

@@ -246,12 +246,74 @@ def params_table(table) -> np.ndarray:
     return t
 
 
-def batched_workspace(n_traj, n_bins: int, device="cuda") -> torch.Tensor:
-    nt = np.ascontiguousarray(n_traj, dtype=np.int32)
-    nbytes = int(_lib.load().abp_batched_workspace_bytes(nt.size, nt.ctypes.data, n_bins))
+def n_tiles(n_traj) -> int:
+    """Tiles of 64 particles over all sets: the size the batched workspace is queried with."""
+    nt = np.asarray(n_traj, dtype=np.int64)
+    return int(((nt + 63) // 64).sum())
+
+
+def batched_workspace(n_sets: int, tiles: int, n_bins: int, device="cuda") -> torch.Tensor:
+    nbytes = int(_lib.load().abp_batched_workspace_bytes(n_sets, tiles, n_bins))
     if nbytes == 0:
         raise ValueError("invalid batched sweep sizes")
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+@dataclass
+class SweepBuffers:
+    """Device tables and outputs of one sweep shape (reused across calls and graph replays)."""
+    params: torch.Tensor   # [n_sets, 9] float64
+    ntraj: torch.Tensor    # [n_sets] int32
+    nsteps: torch.Tensor   # [n_sets] int64
+    window: torch.Tensor | None  # [n_sets] int64, or None for n_steps // 2
+    ws: torch.Tensor
+    out: torch.Tensor      # [n_sets, 2] float64
+    hist: torch.Tensor     # [n_sets, max(bins, 1)] int64 (u64 counts)
+    status: torch.Tensor   # [1] int32, the device-side status
+
+    @staticmethod
+    def make(table, n_traj, n_steps, window=None, bins: int = 256, ws=None,
+             device="cuda") -> "SweepBuffers":
+        t = table if torch.is_tensor(table) else torch.from_numpy(params_table(table))
+        nt = torch.as_tensor(n_traj, dtype=torch.int32)
+        ns = torch.as_tensor(n_steps, dtype=torch.int64)
+        win = None if window is None else torch.as_tensor(window, dtype=torch.int64)
+        if t.ndim != 2 or t.shape[1] != len(PARAM_KEYS):
+            raise ValueError("parameter table must be [n_sets, 9]")
+        n_sets = t.shape[0]
+        if nt.shape != (n_sets,) or ns.shape != (n_sets,):
+            raise ValueError("n_traj and n_steps need one entry per set")
+        if win is not None and win.shape != (n_sets,):
+            raise ValueError("window needs one entry per set")
+        if ws is None:
+            ws = batched_workspace(n_sets, n_tiles(nt.cpu().numpy()), bins, device)
+
+        def dev(x, dtype):
+            return None if x is None else x.to(device=device, dtype=dtype).contiguous()
+
+        out = torch.empty((n_sets, 2), dtype=torch.float64, device=device)
+        hist = torch.empty((n_sets, max(bins, 1)), dtype=torch.int64, device=device)
+        status = torch.empty(1, dtype=torch.int32, device=device)
+        return SweepBuffers(dev(t, torch.float64), dev(nt, torch.int32), dev(ns, torch.int64),
+                            dev(win, torch.int64), ws, out, hist, status)
+
+
+def sweep_enqueue(buf: SweepBuffers, dt: float = 1e-3, scheme="em", seed: int = 11,
+                  bins: int = 256, tune=None, stream=None) -> None:
+    """Enqueue abp_integrate_batched on the buffers' device tables (no host wait; capturable).
+    The device-side status lands in buf.status."""
+    cfg = _lib.AbpBatch(dt, seed, scheme_id(scheme), bins)
+    tn = make_tuning(tune, "batched", scheme)
+    check(_lib.load().abp_integrate_batched(
+        buf.params.shape[0], _ptr(buf.params), _ptr(buf.ntraj), _ptr(buf.nsteps),
+        _ptr(buf.window), ctypes.byref(cfg), ctypes.byref(tn) if tn is not None else None,
+        _ptr(buf.ws), buf.ws.numel(), _ptr(buf.out), _ptr(buf.hist) if bins > 0 else None,
+        _ptr(buf.status), _stream(stream)), "abp_integrate_batched")
+
+
+def check_device_status(status: torch.Tensor, where: str) -> None:
+    """Raise AbpError if a device-side status word holds an error (waits for it)."""
+    check(int(status.item()), where + " (device tables)")
 
 
 def sweep(table, n_traj, n_steps, window=None, dt: float = 1e-3, scheme="em", seed: int = 11,
@@ -259,26 +321,11 @@ def sweep(table, n_traj, n_steps, window=None, dt: float = 1e-3, scheme="em", se
           stream=None) -> SweepResult:
     """One persistent launch over many parameter sets (abp_integrate_batched). Set k runs
     n_traj[k] particles for n_steps[k] steps with Philox set id k and averages over the last
-    window[k] steps (default n_steps[k] // 2)."""
-    t = params_table(table)
-    n_sets = t.shape[0]
-    nt = np.ascontiguousarray(n_traj, dtype=np.int32)
-    ns = np.ascontiguousarray(n_steps, dtype=np.int64)
-    if nt.shape != (n_sets,) or ns.shape != (n_sets,):
-        raise ValueError("n_traj and n_steps need one entry per set")
-    win = None if window is None else np.ascontiguousarray(window, dtype=np.int64)
-    if win is not None and win.shape != (n_sets,):
-        raise ValueError("window needs one entry per set")
-    if ws is None:
-        ws = batched_workspace(nt, bins, device)
-    out = torch.empty((n_sets, 2), dtype=torch.float64, device=device)
-    hist = torch.empty((n_sets, max(bins, 1)), dtype=torch.int64, device=device)
-    cfg = _lib.AbpBatch(dt, seed, scheme_id(scheme), bins)
-    tn = make_tuning(tune, "batched", scheme)
-    check(_lib.load().abp_integrate_batched(
-        n_sets, t.ctypes.data, nt.ctypes.data, ns.ctypes.data,
-        None if win is None else win.ctypes.data, ctypes.byref(cfg),
-        ctypes.byref(tn) if tn is not None else None, _ptr(ws), ws.numel(), _ptr(out),
-        _ptr(hist) if bins > 0 else None, _stream(stream)), "abp_integrate_batched")
-    o = out.cpu().numpy()
-    return SweepResult(o[:, 0].copy(), o[:, 1].copy(), hist[:, :bins])
+    window[k] steps (default n_steps[k] // 2). Host tables are uploaded to the device first."""
+    buf = SweepBuffers.make(table, n_traj, n_steps, window, bins, ws, device)
+    sweep_enqueue(buf, dt, scheme, seed, bins, tune, stream)
+    if stream is not None:
+        stream.synchronize()
+    check_device_status(buf.status, "abp_integrate_batched")
+    o = buf.out.cpu().numpy()
+    return SweepResult(o[:, 0].copy(), o[:, 1].copy(), buf.hist[:, :bins])

@@ -23,12 +23,15 @@
 // and in FP64 across windows (that grouping does not depend on K either); tiles of 64 particles
 // and sets are then reduced in a fixed order.
 //
+// The parameter table is a device array: each call first computes and checks every set's
+// constants on the device (k_adj_rows), raising a status word in the workspace for a set that
+// abp_integrate would reject (or with D <= 0, where the gradient w.r.t. D is undefined); the
+// integration kernels then do nothing and the finalize writes NaN. The call only enqueues.
+//
 // Workspace layout (abp_adjoint_workspace_bytes):
-//   AdjRow rows[n_sets] | float ckpt[n_seg][7][N] | float sub[K/8][7][N] |
+//   AdjRow rows[n_sets] | i32 status | float ckpt[n_seg][7][N] | float sub[K/8][7][N] |
 //   double loss_part[n_sets][tiles][2] | double grad_part[n_sets][tiles][8]
 // (N = n_sets * tiles * 64 checkpoint slots: one per lane, also past a set's last particle)
-#include <vector>
-
 #include "reduce.hpp"
 
 namespace abp {
@@ -54,6 +57,7 @@ struct AdjRow {
 
 struct AdjArgs {
     const AdjRow *rows;
+    const int32_t *status;  // raised by k_adj_rows for an invalid set
     float *ckpt;        // [n_seg][7][N]
     float *sub;         // [K/8][7][N]
     double *loss_part;  // [n_sets][tiles][2]
@@ -79,7 +83,7 @@ constexpr int kMinStage = 8;  // the shortest staging window (sub-checkpoint slo
 constexpr int kGrad = 8;      // gradient components: U0, a, D, d2, q, c, gamma0, F0
 
 struct AdjLayout {
-    size_t rows, ckpt, sub, loss, grad, total;
+    size_t rows, status, ckpt, sub, loss, grad, total;
     int64_t n_seg, n_sub, tiles;
 };
 
@@ -103,7 +107,8 @@ inline AdjLayout adj_layout(int32_t n_sets, int64_t n, int64_t S, int64_t K)
     L.tiles = (n + 63) / 64;
     const size_t N = (size_t)n_sets * (size_t)L.tiles * 64;
     L.rows = 0;
-    L.ckpt = align_up(sizeof(AdjRow) * (size_t)n_sets, 256);
+    L.status = align_up(sizeof(AdjRow) * (size_t)n_sets, 256);
+    L.ckpt = align_up(L.status + sizeof(int32_t), 256);
     L.sub = align_up(L.ckpt + sizeof(float) * 7 * N * (size_t)L.n_seg, 256);
     L.loss = align_up(L.sub + sizeof(float) * 7 * N * (size_t)L.n_sub, 256);
     L.grad = align_up(L.loss + sizeof(double) * 2 * (size_t)n_sets * (size_t)L.tiles, 256);
@@ -175,7 +180,7 @@ template <int SCHEME>
 __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
 {
     Lane L;
-    if (!locate(a, L))
+    if (*a.status != ABP_OK || !locate(a, L))
         return;
     const AdjRow &row = a.rows[L.set];
     const Stream s{a.k0, a.k1, (uint32_t)L.set};
@@ -496,7 +501,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
     constexpr int kStage = NB;
     extern __shared__ float zbuf[];  // ZLDS: [waves per block][z_slots][64]
     Lane L;
-    if (!locate(a, L))
+    if (*a.status != ABP_OK || !locate(a, L))
         return;
     const AdjRow &row = a.rows[L.set];
     const Coef &k = row.k;
@@ -640,10 +645,21 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
 // One block of kFinalizeThreads per set: loss = mean over particles of J_i (the same fixed-order
 // combine as the plain integrator's); grad = gloss / N * sum of tiles, each component summed in
 // the same fixed order.
-__global__ __launch_bounds__(kFinalizeThreads) void k_adj_finalize(AdjArgs a, int32_t phase)
+__global__ __launch_bounds__(kFinalizeThreads) void k_adj_finalize(AdjArgs a, int32_t phase,
+                                                                   int32_t *status)
 {
     const int32_t k = blockIdx.x;
     const int tid = threadIdx.x;
+    const int32_t st = *a.status;
+    if (k == 0 && tid == 0 && status)
+        *status = st;
+    if (st != ABP_OK) {
+        if (phase == 0 && tid == 0)
+            a.loss[k] = __builtin_nan("");
+        if (phase == 1 && tid < kGrad)
+            a.grad[kGrad * (int64_t)k + tid] = __builtin_nan("");
+        return;
+    }
     if (phase == 0) {
         double o[2];
         finalize_set(a.loss_part + 2 * (int64_t)k * a.tiles, a.tiles, a.n, (double)a.W * a.dt, o);
@@ -721,11 +737,11 @@ extern "C" size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set,
     return adj_layout(n_sets, n_per_set, n_steps, ckpt_every).total;
 }
 
-// Per-set constants of both phases, from the FP64 parameters.
-static AdjRow make_adj_row(const abp_params &p, double dt)
+// Per-set constants of both phases, from the FP64 parameters (contraction off, as in make_coef).
+__device__ __forceinline__ AdjRow make_adj_row(const abp_params &p, double dt)
 {
+#pragma clang fp contract(off)
     AdjRow r;
-    std::memset(&r, 0, sizeof r);
     r.k = make_coef(p, dt);
     r.r.two_pi = (float)(2.0 * kPi);
     r.r.four_pi_U0 = (float)(4.0 * kPi * p.U0);
@@ -738,11 +754,12 @@ static AdjRow make_adj_row(const abp_params &p, double dt)
     r.r.g0_dt = (float)(p.gamma0 * dt);
     r.r.c_dt = (float)(p.c * dt);
     r.r.m2d2_dt = (float)(-2.0 * p.d2 * dt);
+    r.pad[0] = r.pad[1] = 0u;
     return r;
 }
 
 // Every FP32 constant of the row is finite (a tiny D makes 1 / (2D) overflow, for instance).
-static bool adj_row_ok(const AdjRow &r)
+__device__ __forceinline__ bool adj_row_ok(const AdjRow &r)
 {
     const RevCoef &c = r.r;
     const float f[] = {c.two_pi, c.four_pi_U0, c.a2, c.eight_a, c.m4pi2U0, c.inv2D,
@@ -753,13 +770,30 @@ static bool adj_row_ok(const AdjRow &r)
     return coef_ok(r.k);
 }
 
-extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_params *h_params,
+// One thread per set: the set's constants, and the status word raised (ABP_E_ARG) if they are
+// invalid. The status word is cleared before this kernel runs.
+__global__ __launch_bounds__(256) void k_adj_rows(int32_t n_sets, const abp_params *params,
+                                                  double dt, AdjRow *rows, int32_t *status)
+{
+    const int32_t k = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n_sets)
+        return;
+    const abp_params p = params[k];
+    const AdjRow r = make_adj_row(p, dt);
+    if (!params_ok(p) || !(p.D > 0.0) || !adj_row_ok(r))
+        atomicMax(status, (int32_t)ABP_E_ARG);
+    rows[k] = r;
+}
+
+extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_params *d_params,
                                   int64_t n_per_set, const abp_adjoint_cfg *cfg, void *d_ws,
                                   size_t ws_bytes, double *d_loss, const double *d_gloss,
-                                  double *d_grad, double *d_grad_particles, void *stream)
+                                  double *d_grad, double *d_grad_particles, int32_t *d_status,
+                                  void *stream)
 {
-    if ((phase != 0 && phase != 1) || !h_params || !cfg || n_sets < 1 || n_per_set < 1 ||
-        (int64_t)n_sets * n_per_set > kMaxParticles || n_per_set > 0xFFFFFFFFll)
+    if ((phase != 0 && phase != 1) || !d_params || !aligned(d_params, 8) || !cfg || n_sets < 1 ||
+        n_per_set < 1 || (int64_t)n_sets * n_per_set > kMaxParticles ||
+        n_per_set > 0xFFFFFFFFll || !aligned(d_status, 4))
         return ABP_E_ARG;
     if (!(cfg->dt > 0.0) || !is_finite(cfg->dt) || cfg->n_steps < 1 ||
         cfg->n_steps > kMaxStepIndex || cfg->window < 1 || cfg->window > cfg->n_steps ||
@@ -768,10 +802,6 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         (cfg->scheme == ABP_HEUN && cfg->lookback > 0) ||
         (cfg->stage_steps != 0 && cfg->stage_steps != 8 && cfg->stage_steps != 16))
         return ABP_E_ARG;
-    for (int32_t k = 0; k < n_sets; ++k)
-        if (!params_ok(h_params[k]) || !(h_params[k].D > 0.0) ||
-            !adj_row_ok(make_adj_row(h_params[k], cfg->dt)))
-            return ABP_E_ARG;
     if (!d_ws || !aligned(d_ws, 256))
         return ABP_E_ARG;
     if (phase == 0 && (!d_loss || !aligned(d_loss, 8)))
@@ -787,18 +817,19 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
     if (abp_status st = check_device())
         return st;
 
-    std::vector<AdjRow> rows((size_t)n_sets);
-    for (int32_t k = 0; k < n_sets; ++k)
-        rows[(size_t)k] = make_adj_row(h_params[k], cfg->dt);
     hipStream_t st = as_stream(stream);
     char *ws = reinterpret_cast<char *>(d_ws);
-    if (hipMemcpyAsync(ws + L.rows, rows.data(), sizeof(AdjRow) * rows.size(),
-                       hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-        return ABP_E_HIP;  // the staged rows live in this call's host memory
+    int32_t *status = reinterpret_cast<int32_t *>(ws + L.status);
+    AdjRow *rows = reinterpret_cast<AdjRow *>(ws + L.rows);
+    fill_u32(reinterpret_cast<uint32_t *>(status), 1, st);
+    hipLaunchKernelGGL(k_adj_rows, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, st, n_sets,
+                       d_params, cfg->dt, rows, status);
+    if (hipGetLastError() != hipSuccess)
+        return ABP_E_HIP;
 
     AdjArgs a{};
-    a.rows = reinterpret_cast<const AdjRow *>(ws + L.rows);
+    a.rows = rows;
+    a.status = status;
     a.ckpt = reinterpret_cast<float *>(ws + L.ckpt);
     a.sub = reinterpret_cast<float *>(ws + L.sub);
     a.loss_part = reinterpret_cast<double *>(ws + L.loss);
@@ -875,6 +906,6 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
     if (hipGetLastError() != hipSuccess)
         return ABP_E_HIP;
     hipLaunchKernelGGL(k_adj_finalize, dim3((unsigned)n_sets), dim3(kFinalizeThreads), 0, st, a,
-                       phase);
+                       phase, d_status);
     return launch_status();
 }

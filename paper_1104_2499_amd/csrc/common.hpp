@@ -23,21 +23,9 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 
 inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-inline bool is_finite(double x) { return std::isfinite(x); }
+__host__ __device__ inline bool is_finite(double x) { return std::isfinite(x); }
 
-// Waits for a stream when it leaves scope once armed: host tables that queued copies read from
-// must outlive those copies on every return path, error returns included.
-struct WaitOnExit {
-    hipStream_t st;
-    bool armed;
-    ~WaitOnExit()
-    {
-        if (armed)
-            (void)hipStreamSynchronize(st);
-    }
-};
-
-inline bool params_ok(const abp_params &p)
+__host__ __device__ inline bool params_ok(const abp_params &p)
 {
     return is_finite(p.U0) && is_finite(p.a) && is_finite(p.phi) && is_finite(p.gamma0) && is_finite(p.F0) &&
            is_finite(p.d2) && is_finite(p.q) && is_finite(p.c) && is_finite(p.D) && p.D >= 0.0;
@@ -55,8 +43,12 @@ abp_status check_device();
 // revolutions (period 1), so it is reduced to [0, 1) in FP64 first: the kernels then add it to
 // positions of magnitude <= 1/2 without losing low bits, and stay inside the hardware cosine's
 // argument range for any finite phase. Phases already in [0, 1) are unchanged.
-inline Coef make_coef(const abp_params &p, double dt)
+// The host (single-set calls) and the device (parameter tables in device memory) compute the
+// same bits: every operation is a correctly rounded FP64 multiply or add taken in source order
+// (contraction into fused multiply-adds is switched off), then one rounding to FP32.
+__host__ __device__ inline Coef make_coef(const abp_params &p, double dt)
 {
+#pragma clang fp contract(off)
     Coef k;
     k.dt = (float)dt;
     k.half_dt = (float)(0.5 * dt);
@@ -75,7 +67,7 @@ inline Coef make_coef(const abp_params &p, double dt)
 // The kernels compute with the FP32 coefficients: a parameter set and time step are accepted only
 // if every coefficient is finite after the conversion and the FP32 time step is positive (finite
 // FP64 values can overflow FP32, and a tiny dt can round to zero).
-inline bool coef_ok(const Coef &k)
+__host__ __device__ inline bool coef_ok(const Coef &k)
 {
     const float f[] = {k.dt, k.half_dt, k.bm, k.phi, k.K1, k.B, k.FH, k.g0, k.d2, k.q, k.c};
     for (float x : f)

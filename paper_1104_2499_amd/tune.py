@@ -98,11 +98,11 @@ def _batched_probe(scheme: str, n_sets: int = 512, step_scale: float = 0.05):
     pick = np.linspace(0, 4095, n_sets).astype(np.int64)
     table, n_traj = table[pick], n_traj[pick]
     n_steps = np.maximum(100, (n_steps[pick] * step_scale).astype(np.int64))
-    ws = api.batched_workspace(n_traj, 256)
+    buf = api.SweepBuffers.make(table, n_traj, n_steps, bins=256)
 
     def make(tune):
         def fn():
-            api.sweep(table, n_traj, n_steps, scheme=scheme, bins=256, tune=tune, ws=ws)
+            api.sweep_enqueue(buf, scheme=scheme, seed=11, bins=256, tune=tune)
         return fn
     return make, float((n_traj.astype(np.int64) * n_steps).sum())
 

@@ -1,8 +1,9 @@
 // abi_client.cpp -- a host program that drives libabp through its C ABI alone (include/abp.h and
 // the HIP runtime's C API; no Python, no torch). It allocates the state, snapshot, reduction
 // workspace and outputs with hipMalloc, runs the initial condition, one integration call with the
-// window snapshot and fused reduction, and the finalize, then prints one JSON line with the
-// results and the status of a call that must be rejected.
+// window snapshot and fused reduction, and the finalize; then a three-set batched sweep whose
+// parameter, trajectory, step and window tables it copies into device memory. It prints one JSON
+// line with the results and the status of calls that must be rejected.
 //
 // usage: abi_client n steps window scheme(0 = EM, 1 = Heun) seed
 #include <hip/hip_runtime_api.h>
@@ -108,10 +109,71 @@ int main(int argc, char **argv)
     const abp_status short_ws = abp_integrate(&p, &r, &s, &snap, d_ws, ws_bytes - 1, bins,
                                               nullptr, nullptr);
 
+    // batched sweep over device tables: U0 varies, sizes are ragged
+    const int32_t n_sets = 3;
+    abp_params h_params[n_sets] = {p, p, p};
+    h_params[1].U0 = 1.5;
+    h_params[2].U0 = 0.7;
+    const int32_t h_ntraj[n_sets] = {(int32_t)n, 100, 65};
+    const int64_t h_nsteps[n_sets] = {steps, 500, 1001};
+    const int64_t h_window[n_sets] = {window, 250, 400};
+    int64_t tiles = 0;
+    for (int k = 0; k < n_sets; ++k)
+        tiles += (h_ntraj[k] + 63) / 64;
+    const size_t bws_bytes = abp_batched_workspace_bytes(n_sets, tiles, bins);
+    abp_params *d_params = nullptr;
+    int32_t *d_ntraj = nullptr, *d_bstatus = nullptr;
+    int64_t *d_nsteps = nullptr, *d_window = nullptr;
+    void *d_bws = nullptr;
+    double *d_bout = nullptr;
+    uint64_t *d_bhist = nullptr;
+    HIP_OK(hipMalloc((void **)&d_params, sizeof h_params));
+    HIP_OK(hipMalloc((void **)&d_ntraj, sizeof h_ntraj));
+    HIP_OK(hipMalloc((void **)&d_nsteps, sizeof h_nsteps));
+    HIP_OK(hipMalloc((void **)&d_window, sizeof h_window));
+    HIP_OK(hipMalloc((void **)&d_bstatus, sizeof(int32_t)));
+    HIP_OK(hipMalloc(&d_bws, bws_bytes));
+    HIP_OK(hipMalloc((void **)&d_bout, 2 * n_sets * sizeof(double)));
+    HIP_OK(hipMalloc((void **)&d_bhist, (size_t)n_sets * bins * sizeof(uint64_t)));
+    HIP_OK(hipMemcpy(d_params, h_params, sizeof h_params, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(d_ntraj, h_ntraj, sizeof h_ntraj, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(d_nsteps, h_nsteps, sizeof h_nsteps, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(d_window, h_window, sizeof h_window, hipMemcpyHostToDevice));
+    abp_batch bcfg = {};
+    bcfg.dt = dt;
+    bcfg.seed = seed;
+    bcfg.scheme = scheme;
+    bcfg.n_bins = bins;
+    ABP_OK_OR_EXIT(abp_integrate_batched(n_sets, d_params, d_ntraj, d_nsteps, d_window, &bcfg,
+                                         nullptr, d_bws, bws_bytes, d_bout, d_bhist, d_bstatus,
+                                         nullptr));
+    double bout[2 * n_sets];
+    int32_t bstatus = -1;
+    HIP_OK(hipMemcpy(bout, d_bout, sizeof bout, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&bstatus, d_bstatus, sizeof bstatus, hipMemcpyDeviceToHost));
+    // a workspace without room for one tile per set is refused on the host
+    const abp_status short_bws = abp_integrate_batched(
+        n_sets, d_params, d_ntraj, d_nsteps, d_window, &bcfg, nullptr, d_bws,
+        abp_batched_workspace_bytes(n_sets, n_sets, bins) - 256, d_bout, d_bhist, d_bstatus,
+        nullptr);
+
     std::printf("{\"abi_version\": %d, \"mean_v\": %.17g, \"stderr\": %.17g, \"hist_total\": %llu, "
-                "\"hist_first\": %llu, \"rejected\": \"%s\", \"short_workspace\": \"%s\"}\n",
+                "\"hist_first\": %llu, \"rejected\": \"%s\", \"short_workspace\": \"%s\", "
+                "\"sweep_status\": %d, \"sweep_mean_v\": [%.17g, %.17g, %.17g], "
+                "\"sweep_stderr\": [%.17g, %.17g, %.17g], \"sweep_short_workspace\": \"%s\"}\n",
                 abp_abi_version(), out[0], out[1], (unsigned long long)total,
-                (unsigned long long)hist[0], abp_status_str(rejected), abp_status_str(short_ws));
+                (unsigned long long)hist[0], abp_status_str(rejected), abp_status_str(short_ws),
+                bstatus, bout[0], bout[2], bout[4], bout[1], bout[3], bout[5],
+                abp_status_str(short_bws));
+
+    HIP_OK(hipFree(d_params));
+    HIP_OK(hipFree(d_ntraj));
+    HIP_OK(hipFree(d_nsteps));
+    HIP_OK(hipFree(d_window));
+    HIP_OK(hipFree(d_bstatus));
+    HIP_OK(hipFree(d_bws));
+    HIP_OK(hipFree(d_bout));
+    HIP_OK(hipFree(d_bhist));
 
     HIP_OK(hipFree(d_ws));
     HIP_OK(hipFree(d_out));

@@ -43,7 +43,7 @@ def gpu():
     from paper_1104_2499_amd import _lib
 
     lib = _lib.load()
-    assert lib.abp_abi_version() == 2
+    assert lib.abp_abi_version() == _lib.ABI_VERSION
     return lib
 
 

@@ -27,7 +27,9 @@ def test_every_declared_symbol_is_exported_and_bound(lib):
 
 
 def test_version_and_status_strings(lib):
-    assert lib.abp_abi_version() == 2
+    from paper_1104_2499_amd import _lib
+
+    assert lib.abp_abi_version() == _lib.ABI_VERSION
     for s in range(5):
         assert lib.abp_status_str(s)
     assert lib.abp_status_str(99) == b"unknown status"
@@ -171,20 +173,70 @@ def test_parameters_that_overflow_fp32_are_rejected(lib):
     assert lib.abp_integrate(ctypes.byref(p), ctypes.byref(tiny_dt), ctypes.byref(s), None, None,
                              0, 0, None, None) == E_ARG
 
-    # batched: one bad set among good ones
-    table = (_lib.AbpParams * 3)(make_params(), make_params(dict(U0=1e39)), make_params())
-    ntraj = (ctypes.c_int32 * 3)(64, 64, 64)
-    nsteps = (ctypes.c_int64 * 3)(100, 100, 100)
-    cfg = _lib.AbpBatch(1e-3, 11, 0, 0)
-    assert lib.abp_integrate_batched(3, table, ntraj, nsteps, None, ctypes.byref(cfg), None,
-                                     0x10000, 1 << 30, 0x1000, None, None) == E_ARG
+    # the batched and adjoint parameter tables live on the device and are checked there
+    # (tests/test_gpu_batched.py, tests/test_gpu_adjoint.py)
 
-    # adjoint: D so small that 1 / (2D) overflows FP32, and a huge U0
+
+def test_batched_and_adjoint_validate_host_arguments(lib):
+    """The scalars, pointers and workspace size of the device-table calls are checked on the host
+    before anything is enqueued; the tables themselves are not read here."""
+    from paper_1104_2499_amd import _lib
+
+    E_ARG, E_WS = _lib.ABP_E_ARG, _lib.ABP_E_WORKSPACE
+    assert lib.abp_batched_workspace_bytes(0, 10, 0) == 0
+    assert lib.abp_batched_workspace_bytes(4, 3, 0) == 0          # fewer tiles than sets
+    assert lib.abp_batched_workspace_bytes(4, 8, 100) == 0        # bins not a power of two
+    assert lib.abp_batched_workspace_bytes(4, 1 << 31, 0) == 0
+    assert lib.abp_batched_workspace_bytes((1 << 20) + 1, 1 << 21, 0) == 0
+    small = lib.abp_batched_workspace_bytes(4, 8, 64)
+    big = lib.abp_batched_workspace_bytes(4, 1000, 64)
+    assert small > 0 and big - small >= 24 * 992  # 8 + 16 bytes per tile
+
+    cfg = _lib.AbpBatch(1e-3, 11, 0, 64)
+    T = 0x10000  # a stand-in device address: nothing is read on these paths
+
+    def batched(n_sets=4, params=T, ntraj=T, nsteps=T, window=None, cfg_=cfg, ws=T,
+                wsb=small, out=T, hist=T, status=None, tune=None):
+        return lib.abp_integrate_batched(n_sets, params, ntraj, nsteps, window,
+                                         ctypes.byref(cfg_) if cfg_ is not None else None,
+                                         ctypes.byref(tune) if tune else None, ws, wsb, out,
+                                         hist, status, None)
+
+    assert batched(n_sets=0) == E_ARG
+    assert batched(params=None) == E_ARG
+    assert batched(params=T + 4) == E_ARG
+    assert batched(ntraj=T + 2) == E_ARG
+    assert batched(nsteps=None) == E_ARG
+    assert batched(window=T + 4) == E_ARG
+    assert batched(status=T + 2) == E_ARG
+    assert batched(cfg_=None) == E_ARG
+    assert batched(cfg_=_lib.AbpBatch(0.0, 11, 0, 64)) == E_ARG
+    assert batched(cfg_=_lib.AbpBatch(1e-3, 11, 2, 64)) == E_ARG
+    assert batched(cfg_=_lib.AbpBatch(1e-3, 11, 0, 48)) == E_ARG
+    assert batched(hist=None) == E_ARG
+    assert batched(ws=T + 128) == E_ARG
+    assert batched(tune=_lib.AbpTuning(256, 1, 1, 9)) == E_ARG
+    # a workspace without room for one tile per set
+    assert batched(wsb=lib.abp_batched_workspace_bytes(4, 4, 64) - 256) == E_WS
+
     acfg = _lib.AbpAdjointCfg(1e-3, 100, 20, 16, 42, 0, 0, 0)
-    for bad in (dict(D=1e-40), dict(U0=1e38)):
-        p1 = (_lib.AbpParams * 1)(make_params(bad))
-        assert lib.abp_adjoint(0, 1, p1, 64, ctypes.byref(acfg), 0x10000, 1 << 30, 0x1000, None,
-                               None, None, None) == E_ARG, bad
+    need = lib.abp_adjoint_workspace_bytes(1, 64, 100, 16)
+
+    def adj(phase=0, params=T, n=64, cfg_=acfg, ws=T, wsb=need, loss=T, gloss=T, grad=T,
+            gp=None, status=None):
+        return lib.abp_adjoint(phase, 1, params, n, ctypes.byref(cfg_), ws, wsb, loss, gloss,
+                               grad, gp, status, None)
+
+    assert adj(params=None) == E_ARG
+    assert adj(params=T + 4) == E_ARG
+    assert adj(loss=None) == E_ARG
+    assert adj(phase=1, gloss=None) == E_ARG
+    assert adj(phase=1, gp=T + 4) == E_ARG
+    assert adj(status=T + 1) == E_ARG
+    assert adj(cfg_=_lib.AbpAdjointCfg(1e-3, 100, 101, 16, 42, 0, 0, 0)) == E_ARG
+    assert adj(cfg_=_lib.AbpAdjointCfg(1e-3, 100, 20, 16, 42, 5, 1, 0)) == E_ARG  # Heun look-back
+    assert adj(cfg_=_lib.AbpAdjointCfg(1e-3, 100, 20, 16, 42, 0, 0, 12)) == E_ARG
+    assert adj(wsb=need - 1) == E_WS
 
 
 def test_ctypes_structs_match_the_c_header(tmp_path):

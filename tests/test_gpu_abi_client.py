@@ -32,8 +32,17 @@ def test_c_client_equals_python_binding(scheme):
 
     res = api.run(BASE_PARAMS, n=n, steps=steps, window=window, scheme=scheme, seed=seed,
                   bins=256)
-    assert got["abi_version"] == 2
+    assert got["abi_version"] == 3
     assert got["mean_v"] == res.mean_v and got["stderr"] == res.stderr
     assert got["hist_total"] == n and got["hist_first"] == int(res.hist[0])
     assert got["rejected"] == "invalid argument"
     assert got["short_workspace"] == "workspace too small"
+    # the batched sweep over device tables: each set equals its single run
+    assert got["sweep_status"] == 0
+    assert got["sweep_short_workspace"] == "workspace too small"
+    sets = [(dict(BASE_PARAMS), n, steps, window), (dict(BASE_PARAMS, U0=1.5), 100, 500, 250),
+            (dict(BASE_PARAMS, U0=0.7), 65, 1001, 400)]
+    for k, (params, n_k, s_k, w_k) in enumerate(sets):
+        r = api.run(params, n=n_k, steps=s_k, window=w_k, scheme=scheme, seed=seed, bins=256,
+                    set_id=k)
+        assert got["sweep_mean_v"][k] == r.mean_v and got["sweep_stderr"][k] == r.stderr

@@ -180,6 +180,33 @@ def test_adjoint_rejects_bad_arguments(gpu):
         adjoint.forward(adjoint.param_rows(_theta(1), cfg2), cfg2, adjoint.workspace(1, cfg))
 
 
+def test_adjoint_device_side_parameter_checks(gpu):
+    """The parameter table is checked on the device in each phase: a set with D <= 0, with
+    1 / (2D) past the FP32 range, or with an FP32-overflowing U0 sets the device status to
+    ABP_E_ARG and turns that call's outputs into NaN; good rows on the same workspace then run."""
+    from paper_1104_2499_amd import _lib, adjoint
+
+    cfg = adjoint.AdjointConfig(n=64, steps=100, window=10, ckpt=16)
+    ws = adjoint.workspace(2, cfg)
+    status = torch.empty(1, dtype=torch.int32, device="cuda")
+    gl = torch.ones(2, dtype=torch.float64, device="cuda")
+    for j, val in ((2, 0.0), (2, 1e-40), (0, 1e38)):
+        theta = _theta(2)
+        theta[1, j] = val
+        rows = adjoint.param_rows(theta, cfg)
+        loss = adjoint.forward(rows, cfg, ws, status=status, check_status=False)
+        assert int(status.item()) == _lib.ABP_E_ARG
+        assert torch.isnan(loss).all()
+        g = adjoint.backward(rows, cfg, ws, gl, status=status, check_status=False)
+        assert int(status.item()) == _lib.ABP_E_ARG
+        assert torch.isnan(g).all()
+    rows = adjoint.param_rows(_theta(2), cfg)
+    loss = adjoint.forward(rows, cfg, ws, status=status, check_status=False)
+    g = adjoint.backward(rows, cfg, ws, gl, status=status, check_status=False)
+    assert int(status.item()) == _lib.ABP_OK
+    assert torch.isfinite(loss).all() and torch.isfinite(g).all()
+
+
 def test_decayed_estimator_matches_oracle(gpu, orc):
     """The look-back-damped estimator (lookback = 500 steps) against the FP64 oracle's, at the
     short horizon and with several sets."""

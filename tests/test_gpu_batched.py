@@ -100,15 +100,56 @@ def test_batched_rejects_bad_arguments(gpu):
     from paper_1104_2499_amd import api
 
     table, n_traj, n_steps, window, _ = _small_sweep()
-    bad = n_traj.copy()
-    bad[3] = 0
     with pytest.raises(ValueError):
-        api.batched_workspace(bad, 32)
+        api.batched_workspace(len(n_traj), len(n_traj) - 1, 32)
+    # a window of zero steps is a bad table entry: found on the device
     with pytest.raises(api.AbpError, match="ABP_E_ARG"):
         api.sweep(table, n_traj, n_steps, window * 0, bins=32)
     ws = torch.empty(64, dtype=torch.uint8, device="cuda")
     with pytest.raises(api.AbpError, match="ABP_E_WORKSPACE"):
         api.sweep(table, n_traj, n_steps, window, bins=32, ws=ws)
+
+
+def test_device_side_table_checks(gpu):
+    """Table values are checked on the device: a set abp_integrate would reject (negative D, an
+    FP32-overflowing U0, no trajectories, too many steps) or a work list longer than the
+    workspace holds sets the device status; nothing is integrated, every mean becomes NaN and
+    every count zero. A good sweep on the same buffers afterwards reports ABP_OK again."""
+    from paper_1104_2499_amd import _lib, api
+
+    table, n_traj, n_steps, window, _ = _small_sweep()
+    col = {k: i for i, k in enumerate(KEYS)}
+    bad_cases = []
+    for key, val in (("D", -0.1), ("U0", 1e39), ("gamma0", float("nan"))):
+        t = table.copy()
+        t[5, col[key]] = val
+        bad_cases.append((t, n_traj, n_steps, _lib.ABP_E_ARG))
+    nt = n_traj.copy()
+    nt[2] = 0
+    bad_cases.append((table, nt, n_steps, _lib.ABP_E_ARG))
+    ns = n_steps.copy()
+    ns[7] = (1 << 34) + 1
+    bad_cases.append((table, n_traj, ns, _lib.ABP_E_ARG))
+    for t, nt, ns, code in bad_cases:
+        buf = api.SweepBuffers.make(t, np.maximum(nt, 1), ns, None, 16)
+        buf.ntraj.copy_(torch.as_tensor(nt))  # the workspace is sized for the valid counts
+        api.sweep_enqueue(buf, bins=16)
+        assert int(buf.status.item()) == code
+        assert torch.isnan(buf.out).all()
+        assert int(buf.hist.abs().sum()) == 0
+    # tiles beyond the workspace: sized for the table, then one set grows
+    buf = api.SweepBuffers.make(table, n_traj, n_steps, window, 16)
+    big = n_traj.copy()
+    big[0] = 64 * 10_000
+    buf.ntraj.copy_(torch.as_tensor(big))
+    api.sweep_enqueue(buf, bins=16)
+    assert int(buf.status.item()) == _lib.ABP_E_WORKSPACE
+    assert torch.isnan(buf.out).all()
+    buf.ntraj.copy_(torch.as_tensor(n_traj))
+    api.sweep_enqueue(buf, bins=16)
+    assert int(buf.status.item()) == _lib.ABP_OK
+    assert torch.isfinite(buf.out).all()
+    assert torch.equal(buf.hist.sum(dim=1).cpu(), torch.as_tensor(n_traj, dtype=torch.int64))
 
 
 def test_autotuner_picks_a_shape_that_changes_no_bits(gpu, tmp_path, monkeypatch):

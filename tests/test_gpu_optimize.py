@@ -25,10 +25,10 @@ def test_adam_loop_small(gpu):
     assert not np.array_equal(r.theta, theta0)
 
 
-def test_adam_loop_with_clipping_and_lookback(gpu):
+def test_adam_loop_with_lookback(gpu):
     from paper_1104_2499_amd import optimize
 
     r = optimize.adam_ratchet(n_sets=4, n=128, steps=1500, window=500, ckpt=64, iters=2, seed=6,
-                              lookback=200, clip_q=0.99)
+                              lookback=200)
     assert np.all(np.isfinite(r.history))
     np.testing.assert_array_equal(r.final_loss, r.verify_mean_v)

@@ -14,8 +14,10 @@ def test_param_rows_places_theta_in_abi_order():
 
     theta = torch.arange(16, dtype=torch.float64).reshape(2, 8) + 1.0
     cfg = adjoint.AdjointConfig(fixed={"phi": 0.25})
-    rows = adjoint.param_rows(theta, cfg)
-    assert rows.shape == (2, len(PARAM_KEYS)) and rows.flags["C_CONTIGUOUS"]
+    rows = adjoint.param_rows(theta, cfg, device="cpu")
+    assert rows.shape == (2, len(PARAM_KEYS)) and rows.is_contiguous()
+    assert rows.dtype == torch.float64
+    rows = rows.numpy()
     for j, key in enumerate(adjoint.GRAD_KEYS):
         np.testing.assert_array_equal(rows[:, PARAM_KEYS.index(key)], theta[:, j].numpy())
     np.testing.assert_array_equal(rows[:, PARAM_KEYS.index("phi")], [0.25, 0.25])
@@ -27,7 +29,8 @@ def test_param_rows_rejects_wrong_width():
     from paper_1104_2499_amd import adjoint
 
     with pytest.raises(ValueError):
-        adjoint.param_rows(torch.zeros(2, 6, dtype=torch.float64), adjoint.AdjointConfig())
+        adjoint.param_rows(torch.zeros(2, 6, dtype=torch.float64), adjoint.AdjointConfig(),
+                           device="cpu")
 
 
 def test_adjoint_config_abi_fields():
@@ -160,4 +163,5 @@ def test_python_layer_rejects_bad_arguments_before_any_device_call():
         adjoint.AdjointConfig(n=64, steps=100, window=10, ckpt=16, scheme="rk4").abi()
     with pytest.raises(ValueError):
         adjoint.param_rows(torch.zeros((2, 6), dtype=torch.float64),
-                           adjoint.AdjointConfig(n=64, steps=100, window=10, ckpt=16))
+                           adjoint.AdjointConfig(n=64, steps=100, window=10, ckpt=16),
+                           device="cpu")
