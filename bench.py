@@ -472,7 +472,7 @@ def main() -> int:
                     help="only run a 512 MiB device copy (reference for HBM counters)")
     ap.add_argument("--tune", default="auto",
                     help='launch shapes: "auto" (the autotuner\'s, tuned once per device and '
-                         'cached), "default" (the library\'s) or block,ppl,unroll')
+                         'cached), "default" (the library\'s) or block,ppl,unroll[,lookahead]')
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint cost measurements (EM and Heun), one JSON line each")
     ap.add_argument("--adjoint-ckpt", type=int, nargs="*", default=None,
@@ -538,8 +538,8 @@ def main() -> int:
             tune_batched = autotune.tune("batched", WORKLOADS["sweep-4096"]["scheme"])
             tune_em = autotune.tune("forward", WORKLOADS["sweep-4096"]["scheme"])
     elif args.tune != "default":
-        b, p, u = (int(t) for t in args.tune.split(","))
-        tune = dict(block=b, ppl=p, unroll=u)
+        fields = [int(t) for t in args.tune.split(",")]
+        tune = dict(zip(("block", "ppl", "unroll", "lookahead"), fields))
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()

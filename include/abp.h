@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define ABP_ABI_VERSION 3
+#define ABP_ABI_VERSION 4
 
 typedef enum abp_status {
     ABP_OK = 0,
@@ -112,9 +112,12 @@ typedef struct abp_state {
 
 /* Launch shape. Zero fields select the built-in default. block: threads per workgroup (64, 128
  * or 256); ppl: particles per lane (1 or 2); unroll: Philox blocks (4 steps each) per loop
- * iteration (1 or 2); waves_per_simd: residency target of the persistent batched launch (1-8). */
+ * iteration (1 or 2); waves_per_simd: residency target of the persistent batched launch (1-8);
+ * lookahead: 1 = each block's noise right before its steps, 2 = the next block's noise computed
+ * while the current block steps (needs unroll 1), 0 = automatic: 2 when the launch holds at most
+ * two wavefronts per SIMD, else 1. No choice changes a bit of the results. */
 typedef struct abp_tuning {
-    int32_t block, ppl, unroll, waves_per_simd;
+    int32_t block, ppl, unroll, waves_per_simd, lookahead;
 } abp_tuning;
 
 int abp_abi_version(void);

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libabp.so")
 
 ABP_OK, ABP_E_ARG, ABP_E_HIP, ABP_E_WORKSPACE, ABP_E_DEVICE = range(5)
 ABP_EM, ABP_HEUN = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 NOALLOC_MAX_PARTICLES = 1 << 24
 STATUS_NAMES = {0: "ABP_OK", 1: "ABP_E_ARG", 2: "ABP_E_HIP", 3: "ABP_E_WORKSPACE",
                 4: "ABP_E_DEVICE"}
@@ -40,7 +40,7 @@ class AbpState(ctypes.Structure):
 
 class AbpTuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("ppl", ctypes.c_int32), ("unroll", ctypes.c_int32),
-                ("waves_per_simd", ctypes.c_int32)]
+                ("waves_per_simd", ctypes.c_int32), ("lookahead", ctypes.c_int32)]
 
 
 class AbpBatch(ctypes.Structure):

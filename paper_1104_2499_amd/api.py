@@ -55,9 +55,11 @@ def make_params(params: dict | None = None) -> _lib.AbpParams:
     return _lib.AbpParams(*[float(d[k]) for k in PARAM_KEYS])
 
 
-def make_tuning(tune, kind: str = "forward", scheme="em") -> _lib.AbpTuning | None:
+def make_tuning(tune, kind: str = "forward", scheme="em", n: int | None = None
+                ) -> _lib.AbpTuning | None:
     """ABI tuning from None (library default), a dict of launch-shape fields, or "auto" (the
-    shape the autotuner cached for this device, kernel kind and scheme; default if none)."""
+    shape the autotuner cached for this device, kernel kind, scheme and -- for an ensemble of n
+    particles -- occupancy band; default if none)."""
     if isinstance(tune, str):
         if tune != "auto":
             raise ValueError('tune must be None, a dict of launch-shape fields, or "auto"')
@@ -65,14 +67,14 @@ def make_tuning(tune, kind: str = "forward", scheme="em") -> _lib.AbpTuning | No
 
         name = scheme.lower() if isinstance(scheme, str) else (
             "em" if scheme == _lib.ABP_EM else "heun")
-        tune = _tune.lookup(kind, name)
+        tune = _tune.lookup(kind, name, n)
     if tune is None:
         return None
     if isinstance(tune, _lib.AbpTuning):
         return tune
     t = dict(tune)
     return _lib.AbpTuning(int(t.get("block", 0)), int(t.get("ppl", 0)), int(t.get("unroll", 0)),
-                          int(t.get("waves_per_simd", 0)))
+                          int(t.get("waves_per_simd", 0)), int(t.get("lookahead", 0)))
 
 
 @dataclass
@@ -173,7 +175,7 @@ def integrate(state: State, n_steps: int, params: dict | None = None, dt: float 
         r.hist_stride, r.d_hist_acc, r.hist_bins = hist_stride, hist_acc.data_ptr(), hist_acc.numel()
     s = state.abi()
     sn = snap.abi() if snap is not None else None
-    t = make_tuning(tune, "forward", scheme)
+    t = make_tuning(tune, "forward", scheme, state.n)
     check(_lib.load().abp_integrate(ctypes.byref(p), ctypes.byref(r), ctypes.byref(s),
                                     ctypes.byref(sn) if sn is not None else None, _ptr(ws),
                                     0 if ws is None else ws.numel(), n_bins,

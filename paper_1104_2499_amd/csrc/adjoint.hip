@@ -176,7 +176,7 @@ __device__ __forceinline__ Particle initial_particle(uint32_t pid, uint32_t set,
 }
 
 // Forward phase: integrate, store a checkpoint at every multiple of K, reduce the loss.
-template <int SCHEME>
+template <int SCHEME, int LOOP>
 __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
 {
     Lane L;
@@ -193,10 +193,10 @@ __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
         put_state(a.ckpt + (size_t)j * 7 * a.N, a.N, L.g, p[0]);
         const int64_t end = (j + 1) * a.K < a.S ? (j + 1) * a.K : a.S;
         if (wb >= step && wb < end) {
-            advance<SCHEME, 1, 1>(row.k, s, pid, p, step, wb);
+            advance<SCHEME, 1, LOOP>(row.k, s, pid, p, step, wb);
             xs[0] = position64(p[0].cell, p[0].xf, p[0].lx);
         }
-        advance<SCHEME, 1, 1>(row.k, s, pid, p, step, end);
+        advance<SCHEME, 1, LOOP>(row.k, s, pid, p, step, end);
     }
     if (wb == a.S)
         xs[0] = position64(p[0].cell, p[0].xf, p[0].lx);
@@ -855,10 +855,18 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
     const unsigned grid = (unsigned)((waves * 64 + 255) / 256);
     const bool heun = cfg->scheme == ABP_HEUN;
     if (phase == 0) {
-        if (heun)
-            hipLaunchKernelGGL(k_adj_forward<1>, dim3(grid), dim3(256), 0, st, a);
+        // the noise of the next block ahead of the steps when the grid holds at most two
+        // wavefronts per SIMD (its own instruction stream is all a SIMD has), else in place
+        const int cus = device_cus();
+        const bool ahead = cus > 0 && waves <= (int64_t)cus * 4 * 2;
+        if (heun && ahead)
+            hipLaunchKernelGGL((k_adj_forward<1, kAhead>), dim3(grid), dim3(256), 0, st, a);
+        else if (heun)
+            hipLaunchKernelGGL((k_adj_forward<1, 1>), dim3(grid), dim3(256), 0, st, a);
+        else if (ahead)
+            hipLaunchKernelGGL((k_adj_forward<0, kAhead>), dim3(grid), dim3(256), 0, st, a);
         else
-            hipLaunchKernelGGL(k_adj_forward<0>, dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_adj_forward<0, 1>), dim3(grid), dim3(256), 0, st, a);
     } else {
         // B = 16 is the default for both schemes: one wavefront per SIMD. B = 8 (on request) fits
         // two Euler-Maruyama wavefronts per SIMD; the Heun backward runs one wavefront per SIMD at

@@ -28,6 +28,25 @@ abp_status check_device()
 }
 
 // x0 = (w0 >> 8) 2^-24 of Philox block (0, id, set, 1); v0 = e0 = 0.
+int device_cus()
+{
+    static std::atomic<int> cache[64];  // 0 = unknown
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 0;
+    if (dev >= 0 && dev < 64) {
+        const int known = cache[dev].load(std::memory_order_relaxed);
+        if (known)
+            return known;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (dev >= 0 && dev < 64)
+        cache[dev].store(cus, std::memory_order_relaxed);
+    return cus;
+}
+
 __global__ __launch_bounds__(256) void k_init_state(int32_t *cell, float *xf, float *v, float *e,
                                                     float *lo, int64_t n, uint32_t id0,
                                                     uint32_t set, uint32_t k0, uint32_t k1)

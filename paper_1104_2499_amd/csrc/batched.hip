@@ -316,23 +316,26 @@ static void launch_batched(const BatchArgs &a, int block, int grid, hipStream_t 
     hipLaunchKernelGGL((k_batched<SCHEME, PPL, UNROLL>), dim3(grid), dim3(block), 0, st, a);
 }
 
-template <int SCHEME>
-static void dispatch_batched(const BatchArgs &a, const Shape &sh, int grid, hipStream_t st)
+template <int SCHEME, int PPL>
+static void dispatch_loop(const BatchArgs &a, const Shape &sh, int grid, hipStream_t st)
 {
-    if (sh.ppl == 1) {
-        if (sh.unroll == 1)
-            launch_batched<SCHEME, 1, 1>(a, sh.block, grid, st);
-        else
-            launch_batched<SCHEME, 1, 2>(a, sh.block, grid, st);
-    } else {
-        if (sh.unroll == 1)
-            launch_batched<SCHEME, 2, 1>(a, sh.block, grid, st);
-        else
-            launch_batched<SCHEME, 2, 2>(a, sh.block, grid, st);
+    switch (sh.loop()) {
+    case 1: launch_batched<SCHEME, PPL, 1>(a, sh.block, grid, st); break;
+    case 2: launch_batched<SCHEME, PPL, 2>(a, sh.block, grid, st); break;
+    default: launch_batched<SCHEME, PPL, kAhead>(a, sh.block, grid, st); break;
     }
 }
 
-constexpr Shape kDefaultBatched = {256, 1, 1, 8};
+template <int SCHEME>
+static void dispatch_batched(const BatchArgs &a, const Shape &sh, int grid, hipStream_t st)
+{
+    if (sh.ppl == 1)
+        dispatch_loop<SCHEME, 1>(a, sh, grid, st);
+    else
+        dispatch_loop<SCHEME, 2>(a, sh, grid, st);
+}
+
+constexpr Shape kDefaultBatched = {256, 1, 1, 8, 0};
 constexpr int32_t kMaxSets = 1 << 20;
 
 }  // namespace abp
@@ -414,6 +417,7 @@ extern "C" abp_status abp_integrate_batched(int32_t n_sets, const abp_params *d_
     const int waves_per_block = sh.block / 64;
     const int64_t grid = std::max<int64_t>(1, (int64_t)cus * 4 * sh.waves_per_simd /
                                                   waves_per_block);
+    resolve_lookahead(sh, grid * waves_per_block);
     if (cfg->scheme == ABP_EM)
         dispatch_batched<0>(a, sh, (int)grid, st);
     else

@@ -97,8 +97,10 @@ inline bool state_ok(const abp_state *s)
     return (uint64_t)s->id0 + (uint64_t)(s->n - 1) <= 0xFFFFFFFFull;
 }
 
+// Launch shape; loop = the advance() loop form: 1 or 2 blocks per trip, or kAhead.
 struct Shape {
-    int block, ppl, unroll, waves_per_simd;
+    int block, ppl, unroll, waves_per_simd, lookahead;
+    int loop() const { return lookahead == 2 ? kAhead : unroll; }
 };
 
 inline bool resolve_tuning(const abp_tuning *t, Shape def, Shape &out)
@@ -114,13 +116,30 @@ inline bool resolve_tuning(const abp_tuning *t, Shape def, Shape &out)
         out.unroll = t->unroll;
     if (t->waves_per_simd)
         out.waves_per_simd = t->waves_per_simd;
+    if (t->lookahead)
+        out.lookahead = t->lookahead;
     if (out.block != 64 && out.block != 128 && out.block != 256)
         return false;
     if (out.ppl != 1 && out.ppl != 2)
         return false;
     if (out.unroll != 1 && out.unroll != 2)
         return false;
+    if (out.lookahead < 0 || out.lookahead > 2 || (out.lookahead == 2 && out.unroll != 1))
+        return false;
     return out.waves_per_simd >= 1 && out.waves_per_simd <= 8;
+}
+
+// Compute units of the current device (cached per device ordinal); 0 if the query fails.
+int device_cus();
+
+// The automatic look-ahead choice (lookahead = 0): on when `waves` wavefronts fill at most two per
+// SIMD of the device, where a wavefront's own instruction stream is all a SIMD has to issue.
+inline void resolve_lookahead(Shape &sh, int64_t waves)
+{
+    if (sh.lookahead != 0)
+        return;
+    const int cus = device_cus();
+    sh.lookahead = (sh.unroll == 1 && cus > 0 && waves <= (int64_t)cus * 4 * 2) ? 2 : 1;
 }
 
 inline abp_status launch_status()

@@ -201,11 +201,29 @@ struct Stream {
     uint32_t set;
 };
 
+// One aligned block of four steps of one particle with the block's noise z, then the block end.
+template <int SCHEME>
+__device__ __forceinline__ void block_steps(const Coef &k, Particle &p, const Noise4 &z)
+{
+    const float xb = p.xf + k.phi;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        step<SCHEME>(k, p, xb, z.z[j]);
+    end_block(p);
+}
+
 // Advance PPL particles of one lane from absolute step n to `stop` (both wavefront-uniform).
 // Blocks of four steps aligned on absolute indices take the fast path; a call that starts or
 // ends inside a block handles its partial block step by step. Block ends (renormalisation and
 // wrap) happen only after absolute steps 4b+3, so any split of a run into calls gives
 // bit-identical states.
+// Loop forms (all compute the same values): LOOP = 1, each block's noise right before its steps;
+// LOOP = 2, two blocks' noise per loop trip, then their steps; LOOP = kAhead, the noise of block
+// b+1 (Philox and Box-Muller, which do not depend on the state) computed while block b steps, so
+// that the two dependency chains overlap in one instruction stream -- for launches that hold one
+// or two wavefronts per SIMD, where a wavefront's own instruction stream is all the SIMD has.
+constexpr int kAhead = 3;
+
 template <int SCHEME, int PPL, int UNROLL>
 __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const uint32_t (&pid)[PPL],
                                         Particle (&p)[PPL], int64_t &n, int64_t stop)
@@ -229,33 +247,51 @@ __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const ui
     // aligned blocks
     const int64_t nblk = (stop - n) >> 2;
     uint32_t blk = (uint32_t)(n >> 2);
-    int64_t b = 0;
-    for (; b + UNROLL <= nblk; b += UNROLL) {
+    if constexpr (UNROLL == kAhead) {
+        if (nblk > 0) {
+            Noise4 z[PPL];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
+            for (int q = 0; q < PPL; ++q)
+                z[q] = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
+            for (int64_t b = 1; b < nblk; ++b) {
+                Noise4 zn[PPL];
+#pragma unroll
+                for (int q = 0; q < PPL; ++q)
+                    zn[q] = noise_block(blk + 1, pid[q], s.set, s.k0, s.k1, k.bm);
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) {
+                    block_steps<SCHEME>(k, p[q], z[q]);
+                    z[q] = zn[q];
+                }
+                ++blk;
+            }
+            // the last aligned block (a trailing partial block draws its own noise)
+#pragma unroll
+            for (int q = 0; q < PPL; ++q)
+                block_steps<SCHEME>(k, p[q], z[q]);
+            ++blk;
+        }
+    } else {
+        int64_t b = 0;
+        for (; b + UNROLL <= nblk; b += UNROLL) {
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) {
+                    const Noise4 z = noise_block(blk + u, pid[q], s.set, s.k0, s.k1, k.bm);
+                    block_steps<SCHEME>(k, p[q], z);
+                }
+            }
+            blk += UNROLL;
+        }
+        for (; b < nblk; ++b) {
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
-                const Noise4 z = noise_block(blk + u, pid[q], s.set, s.k0, s.k1, k.bm);
-                const float xb = p[q].xf + k.phi;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    step<SCHEME>(k, p[q], xb, z.z[j]);
-                end_block(p[q]);
+                const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
+                block_steps<SCHEME>(k, p[q], z);
             }
+            ++blk;
         }
-        blk += UNROLL;
-    }
-    for (; b < nblk; ++b) {
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
-            const float xb = p[q].xf + k.phi;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                step<SCHEME>(k, p[q], xb, z.z[j]);
-            end_block(p[q]);
-        }
-        ++blk;
     }
     n += nblk << 2;
     // trailing partial block (its end is taken by the call that finishes the block)

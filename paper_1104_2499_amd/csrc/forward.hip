@@ -222,27 +222,30 @@ static void launch_integrate(const FwdArgs &a, int block, hipStream_t st)
                        st, a);
 }
 
-// The time-histogram variant runs one particle per lane and no unrolling (its results, like
+// The time-histogram variant runs one particle per lane and the in-place loop (its results, like
 // every variant's, do not depend on the launch shape); only the block size is taken from tuning.
-template <int SCHEME>
-static void dispatch_integrate(const FwdArgs &a, const Shape &sh, hipStream_t st)
+template <int SCHEME, int PPL>
+static void dispatch_loop(const FwdArgs &a, const Shape &sh, hipStream_t st)
 {
-    if (a.acc_stride > 0) {
-        launch_integrate<SCHEME, 1, 1, true>(a, sh.block, st);
-    } else if (sh.ppl == 1) {
-        if (sh.unroll == 1)
-            launch_integrate<SCHEME, 1, 1>(a, sh.block, st);
-        else
-            launch_integrate<SCHEME, 1, 2>(a, sh.block, st);
-    } else {
-        if (sh.unroll == 1)
-            launch_integrate<SCHEME, 2, 1>(a, sh.block, st);
-        else
-            launch_integrate<SCHEME, 2, 2>(a, sh.block, st);
+    switch (sh.loop()) {
+    case 1: launch_integrate<SCHEME, PPL, 1>(a, sh.block, st); break;
+    case 2: launch_integrate<SCHEME, PPL, 2>(a, sh.block, st); break;
+    default: launch_integrate<SCHEME, PPL, kAhead>(a, sh.block, st); break;
     }
 }
 
-constexpr Shape kDefaultForward = {256, 1, 1, 8};
+template <int SCHEME>
+static void dispatch_integrate(const FwdArgs &a, const Shape &sh, hipStream_t st)
+{
+    if (a.acc_stride > 0)
+        launch_integrate<SCHEME, 1, 1, true>(a, sh.block, st);
+    else if (sh.ppl == 1)
+        dispatch_loop<SCHEME, 1>(a, sh, st);
+    else
+        dispatch_loop<SCHEME, 2>(a, sh, st);
+}
+
+constexpr Shape kDefaultForward = {256, 1, 1, 8, 0};
 
 static void zero_hist(uint32_t *hist, int32_t n_bins, hipStream_t st)
 {
@@ -302,6 +305,7 @@ static abp_status plan_integrate(const abp_params *p, const abp_run *r, const ab
         return ABP_E_ARG;
     if (!resolve_tuning(tune, kDefaultForward, sh))
         return ABP_E_ARG;
+    resolve_lookahead(sh, (s->n + 64 * sh.ppl - 1) / (64 * sh.ppl));
 
     a = FwdArgs{};
     a.st = view(s);

@@ -1,7 +1,12 @@
 """Autotuner for the launch shape of the integrators.
 
-A candidate is (block, ppl, unroll, waves_per_simd): threads per workgroup, particles per lane,
-Philox blocks per loop trip, and (for the persistent sweep) the residency the grid is sized for.
+A candidate is (block, ppl, unroll, lookahead, waves_per_simd): threads per workgroup, particles
+per lane, the loop form (one or two Philox blocks per trip, or the next block's noise computed
+ahead of the steps) and (for the persistent sweep) the residency the grid is sized for.
+The single-set integrator is tuned for two occupancy bands, because the best loop form differs:
+"forward" on 2^20 particles (16 wavefronts per SIMD: issue-bound) and "forward-small" on 65536
+(one wavefront per SIMD, where a wavefront's own instruction stream is all a SIMD issues);
+lookups for ensembles of at most two wavefronts per SIMD use the small band's entry.
 Every candidate computes bit-identical results (the reductions are tiled independently of the
 launch shape), so the tuner only times them: each candidate runs a short probe workload after a
 warm-up launch, timed with HIP events on the launch stream, and the fastest is kept.
@@ -60,10 +65,19 @@ def _store_cache(cache: dict) -> bool:
     return True
 
 
+LOOPS = ((1, 1), (2, 1), (1, 2))  # (unroll, lookahead)
+
+
 def candidates(kind: str):
     waves = WAVES if kind == "batched" else (8,)
-    for block, ppl, unroll, wps in itertools.product(BLOCKS, PPLS, UNROLLS, waves):
-        yield dict(block=block, ppl=ppl, unroll=unroll, waves_per_simd=wps)
+    for block, ppl, (unroll, la), wps in itertools.product(BLOCKS, PPLS, LOOPS, waves):
+        yield dict(block=block, ppl=ppl, unroll=unroll, lookahead=la, waves_per_simd=wps)
+
+
+def small_band_limit() -> int:
+    """Largest ensemble that fills at most two wavefronts per SIMD of the current device."""
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return p.multi_processor_count * 4 * 2 * 64
 
 
 def _time(fn, reps: int = 2) -> float:
@@ -115,8 +129,12 @@ def tune(kind: str = "forward", scheme: str = "heun", force: bool = False,
     cache = _load_cache()
     if not force and key in cache:
         return cache[key]["tune"]
-    make, work = (_forward_probe if kind == "forward" else _batched_probe)(scheme,
-                                                                           **(probe or {}))
+    if kind == "forward-small":
+        make, work = _forward_probe(scheme, **(probe or dict(n=65536, steps=4000)))
+    elif kind == "forward":
+        make, work = _forward_probe(scheme, **(probe or {}))
+    else:
+        make, work = _batched_probe(scheme, **(probe or {}))
     results = []
     for cand in candidates(kind):
         ms = _time(make(cand))
@@ -131,9 +149,15 @@ def tune(kind: str = "forward", scheme: str = "heun", force: bool = False,
     return best
 
 
-def lookup(kind: str, scheme: str) -> dict | None:
-    """The cached shape, or None if this device has not been tuned."""
-    entry = _load_cache().get(device_key(kind, scheme))
+def lookup(kind: str, scheme: str, n: int | None = None) -> dict | None:
+    """The cached shape, or None if this device has not been tuned. For the single-set
+    integrator, an ensemble of n particles within the small band uses that band's entry."""
+    cache = _load_cache()
+    if kind == "forward" and n is not None and n <= small_band_limit():
+        entry = cache.get(device_key("forward-small", scheme))
+        if entry is not None:
+            return entry["tune"]
+    entry = cache.get(device_key(kind, scheme))
     return None if entry is None else entry["tune"]
 
 
@@ -141,11 +165,12 @@ if __name__ == "__main__":
     import argparse
 
     ap = argparse.ArgumentParser(description="tune the launch shapes and cache the result")
-    ap.add_argument("--kind", choices=["forward", "batched", "all"], default="all")
+    ap.add_argument("--kind", choices=["forward", "forward-small", "batched", "all"],
+                    default="all")
     ap.add_argument("--scheme", choices=["em", "heun", "all"], default="all")
     ap.add_argument("--force", action="store_true")
     args = ap.parse_args()
-    kinds = ["forward", "batched"] if args.kind == "all" else [args.kind]
+    kinds = ["forward", "forward-small", "batched"] if args.kind == "all" else [args.kind]
     schemes = ["em", "heun"] if args.scheme == "all" else [args.scheme]
     for k in kinds:
         for s in schemes:

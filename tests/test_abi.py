@@ -111,6 +111,8 @@ def test_integrate_rejects_bad_arguments_without_a_device(lib):
     assert call(tune=_lib.AbpTuning(96, 1, 1, 0)) == E_ARG
     assert call(tune=_lib.AbpTuning(256, 3, 1, 0)) == E_ARG
     assert call(tune=_lib.AbpTuning(256, 1, 4, 0)) == E_ARG
+    assert call(tune=_lib.AbpTuning(256, 1, 2, 0, 2)) == E_ARG  # look-ahead needs unroll 1
+    assert call(tune=_lib.AbpTuning(256, 1, 1, 0, 3)) == E_ARG
 
 
 def test_valid_call_without_gpu_reports_device(lib):

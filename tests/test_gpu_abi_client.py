@@ -32,7 +32,7 @@ def test_c_client_equals_python_binding(scheme):
 
     res = api.run(BASE_PARAMS, n=n, steps=steps, window=window, scheme=scheme, seed=seed,
                   bins=256)
-    assert got["abi_version"] == 3
+    assert got["abi_version"] == 4
     assert got["mean_v"] == res.mean_v and got["stderr"] == res.stderr
     assert got["hist_total"] == n and got["hist_first"] == int(res.hist[0])
     assert got["rejected"] == "invalid argument"

@@ -40,13 +40,13 @@ def test_each_set_equals_its_single_run_for_every_tuning(gpu, scheme):
              for k in range(len(n_traj))]
     for block in (64, 256):
         for ppl in (1, 2):
-            for unroll in (1, 2):
+            for unroll, la in ((1, 1), (1, 2), (2, 1)):
                 for wps in (1, 8):
                     r = api.sweep(table, n_traj, n_steps, window, scheme=scheme, seed=seed,
                                   bins=bins, tune=dict(block=block, ppl=ppl, unroll=unroll,
-                                                       waves_per_simd=wps))
+                                                       waves_per_simd=wps, lookahead=la))
                     for k, a in enumerate(alone):
-                        assert r.mean_v[k] == a.mean_v, (k, block, ppl, unroll, wps)
+                        assert r.mean_v[k] == a.mean_v, (k, block, ppl, unroll, la, wps)
                         assert r.stderr[k] == a.stderr
                         assert torch.equal(r.hist[k], a.hist)
 
@@ -159,11 +159,16 @@ def test_autotuner_picks_a_shape_that_changes_no_bits(gpu, tmp_path, monkeypatch
     from paper_1104_2499_amd import api, tune
 
     monkeypatch.setenv("ABP_TUNE_CACHE", str(tmp_path / "tune.json"))
-    best_f = tune.tune("forward", "em", force=True, probe=dict(n=65536, steps=400))
+    best_f = tune.tune("forward", "em", force=True, probe=dict(n=65536 * 4, steps=400))
+    best_s = tune.tune("forward-small", "em", force=True, probe=dict(n=16384, steps=400))
     best_b = tune.tune("batched", "em", force=True, probe=dict(n_sets=64, step_scale=0.01))
     assert best_f in list(tune.candidates("forward"))
+    assert best_s in list(tune.candidates("forward"))
     assert best_b in list(tune.candidates("batched"))
     assert tune.lookup("forward", "em") == best_f and tune.lookup("batched", "em") == best_b
+    # ensembles within two wavefronts per SIMD take the small band's shape
+    assert tune.lookup("forward", "em", n=tune.small_band_limit()) == best_s
+    assert tune.lookup("forward", "em", n=tune.small_band_limit() + 1) == best_f
     a = api.run(None, n=3000, steps=1001, scheme="em", seed=3, bins=64, tune="auto")
     b = api.run(None, n=3000, steps=1001, scheme="em", seed=3, bins=64)
     assert a.mean_v == b.mean_v and a.stderr == b.stderr and torch.equal(a.hist, b.hist)

@@ -349,15 +349,18 @@ def test_chunked_equals_unchunked_bitwise(gpu, scheme):
     assert torch.equal(hist, one.hist)
 
 
-def test_every_tuning_gives_identical_results(gpu):
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_every_tuning_gives_identical_results(gpu, scheme):
+    """Every launch shape -- block size, particles per lane, and the loop form (one or two noise
+    blocks per trip, or the next block's noise ahead of the steps) -- gives the same bits."""
     from paper_1104_2499_amd import api
 
     ref = None
     for block in (64, 128, 256):
         for ppl in (1, 2):
-            for unroll in (1, 2):
-                r = api.run(BASE, n=5000, steps=403, window=201, scheme="heun", seed=3, bins=128,
-                            tune=dict(block=block, ppl=ppl, unroll=unroll))
+            for unroll, lookahead in ((1, 1), (1, 2), (2, 1), (1, 0)):
+                r = api.run(BASE, n=5000, steps=403, window=201, scheme=scheme, seed=3, bins=128,
+                            tune=dict(block=block, ppl=ppl, unroll=unroll, lookahead=lookahead))
                 got = tuple(_np(t) for t in r.state.tensors()) + (r.mean_v, r.stderr,
                                                                    _np(r.hist))
                 if ref is None:

@@ -68,7 +68,7 @@ def test_tuner_candidates_are_valid_launch_shapes(lib):
     r = _lib.AbpRun(1e-3, 100, 0, -1, 42, 0, 0)
     p = make_params()
     shapes = list(tune.candidates("forward")) + list(tune.candidates("batched"))
-    assert len(shapes) == 12 + 24
+    assert len(shapes) == 18 + 36  # 3 blocks x 2 ppl x 3 loop forms (x 2 residencies)
     for shape in shapes:
         t = make_tuning(shape)
         rc = lib.abp_integrate(ctypes.byref(p), ctypes.byref(r), ctypes.byref(s), None, None, 0, 0,
