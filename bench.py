@@ -26,9 +26,6 @@ sys.path.insert(0, ROOT)
 N_SIMD = 256 * 4
 CLOCK_HZ = 2.4e9
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-# Issue rate of one wave64 VALU instruction per SIMD every 4 cycles (the rate at which the hot loop
-# is measured to run: SQ_INSTS_VALU per second per SIMD = CLOCK_HZ / 4).
-VALU_LANE_INSTR_PER_S = N_SIMD * 64 * CLOCK_HZ / 4
 
 # Algorithmic FP32 FLOPs of the method per particle-step (FMA = 2): drift 14 (phase add, 2 FMAs for
 # F0 - U', 2 for f_v, mul + 2 FMAs for f_e), EM update 7, Heun predictor 7 + corrector 10 + a second
@@ -47,17 +44,26 @@ COUNTED_FLOP_PER_STEP = dict(em=30.75, heun=54.75)
 # Issue time of v_cos/v_sin/v_log/v_sqrt_f32 per wave64 instruction per SIMD, measured by
 # ubench/valu_rates.hip (profiles/valu_issue_rates.txt).
 TRANS_NS_PER_WAVE_INSTR = 3.45
-# VALU instructions of each issue class per 4-step loop trip of k_integrate<scheme, 1, 1> (gfx950
-# ISA; for Heun equal, class by class, to the SQ_INSTS_VALU_* counters) and the issue time of each
-# class per wave64 instruction per SIMD measured by ubench/valu_rates.hip, in ns: FMA reading
-# three VGPRs, FMA with an SGPR/constant operand, FP32 add/sub and mul, transcendental,
-# v_mad_u64_u32, v_bitop3_b32, and the rest (alignbit, xor, rint, cvt, moves; costed as an integer
-# add).
-LOOP_CLASS_COUNTS = dict(
-    heun=dict(fma3=8, fma=64, add=45, mul=14, trans=16, mad64=15, bitop3=14, other=12),
-    em=dict(fma3=4, fma=32, add=29, mul=10, trans=12, mad64=15, bitop3=14, other=12))
-CLASS_NS = dict(fma3=1.5315, fma=1.0493, add=0.9959, mul=0.9540, trans=3.4536, mad64=1.4587,
-                bitop3=1.7200, other=1.0500)
+UBENCH = os.path.join(ROOT, "paper_1104_2499_amd", "ubench", "valu_rates")
+
+
+def mix_ceiling() -> dict:
+    """The measured issue ceiling of the integrators' own instruction mix: ubench/valu_rates
+    --mix replays one 4-step loop trip of k_integrate (its gfx950 instruction sequence) on
+    registers that never wait for each other, at 1, 2, 4 and 8 wavefronts per SIMD; returns
+    {scheme: {waves_per_simd: ns per trip per wavefront per SIMD}}. Run as a child process."""
+    import subprocess
+
+    res = subprocess.run([UBENCH, "--mix"], capture_output=True, text=True, timeout=120)
+    if res.returncode != 0:
+        raise RuntimeError("valu_rates --mix failed: " + res.stderr[-500:])
+    out: dict = {}
+    for line in res.stdout.splitlines():
+        if line.startswith("mix_"):
+            key, val = line.split(":")
+            _, scheme, _, _, w = key.split("_")  # mix_<scheme>_trip_ns_w<W>
+            out.setdefault(scheme, {})[int(w[1:])] = float(val)
+    return out
 
 
 KERNEL_SOURCES = ("common.hpp", "device.hpp", "reduce.hpp", "forward.hip")
@@ -117,7 +123,7 @@ def cpu_baseline(wl: dict, params: dict, seconds_budget: float = 15.0) -> dict:
     oracle.reduce(xs, xe, wl["window"] * wl["dt"], wl["bins"])
     dt_s = time.perf_counter() - t0
     return {"value": n * steps / dt_s, "unit": "particle-steps/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": _host_cpu(),
             "sample": f"{n} of {wl['n']} particles (evenly spaced ids), full {steps} steps, "
                       f"{dt_s:.1f} s"}
 
@@ -411,6 +417,7 @@ def adjoint_bench(reps: int = 10, scheme: str = "em", ckpt: int | None = None) -
             "workspace_bytes": int(ws.numel()), "plain_forward_ms": t_plain,
             "adjoint_forward_ms": t_fwd,
             "adjoint_backward_ms": t_bwd, "cost_ratio": (t_fwd + t_bwd) / t_plain,
+            "plain_forward_particle_steps_per_s": n * S / (t_plain * 1e-3),
             "loss_equals_forward_mean": loss == mean_v,
             "particle_steps": n * S}
 
@@ -455,6 +462,46 @@ def adjoint_batched_bench(stage: int, ckpt: int, reps: int = 3) -> dict:
             "workspace_bytes": nbytes,
             "forward_ms": float(np.median([t[0] for t in times])),
             "backward_ms": float(np.median([t[1] for t in times]))}
+
+
+def adjoint_batched_item(iters: int = 50) -> dict:
+    """The batched-adjoint workload (1024 sets x 1024 particles x 5e4 EM steps, W = 1e4; K = 80,
+    8-step staging): one forward + backward iteration against the plain batched forward of the
+    same sets, then the 50-iteration Adam loop on (U0, a, d2) with the exact pathwise gradient."""
+    import numpy as np
+    import torch
+
+    from paper_1104_2499_amd import api, optimize
+    from paper_1104_2499_amd.adjoint import AdjointConfig, param_rows
+    from paper_1104_2499_amd.workloads import WORKLOADS
+
+    wl = WORKLOADS["adjoint-batched-1k"]
+    it = adjoint_batched_bench(wl["stage"], wl["ckpt"], reps=2)
+    # the plain batched integrator on the same sets and initial parameters
+    theta = torch.tensor(optimize.initial_theta(wl["n_sets"], wl["seed"]))
+    cfg = AdjointConfig(n=wl["n"], steps=wl["steps"], window=wl["window"], seed=wl["seed"])
+    buf = api.SweepBuffers.make(param_rows(theta, cfg), np.full(wl["n_sets"], wl["n"], np.int32),
+                                np.full(wl["n_sets"], wl["steps"], np.int64),
+                                np.full(wl["n_sets"], wl["window"], np.int64), bins=0)
+
+    def plain():
+        api.sweep_enqueue(buf, wl["dt"], "em", wl["seed"], 0)
+    plain_ms = _gpu_ms(plain, 2)
+    api.check_device_status(buf.status, "sweep")
+    del buf
+    r = optimize.adam_ratchet(wl["n_sets"], wl["n"], wl["steps"], wl["window"], wl["ckpt"],
+                              iters, wl["seed"], stage=wl["stage"])
+    torch.cuda.empty_cache()
+    return {"workload": "adjoint-batched-1k", "scheme": "em", "ckpt": wl["ckpt"],
+            "stage": wl["stage"], "forward_ms": it["forward_ms"], "backward_ms": it["backward_ms"],
+            "plain_forward_ms": plain_ms,
+            "cost_ratio": (it["forward_ms"] + it["backward_ms"]) / plain_ms,
+            "adam": {"iterations": iters, "estimator": "exact pathwise gradient",
+                     "seconds": r.seconds, "mean_abs_v_start": float(r.history[0]),
+                     "mean_abs_v_end": float(r.history[-1]),
+                     "mean_abs_v_rose": bool(r.history[-1] > r.history[0]),
+                     "final_loss_equals_plain_forward": bool(np.array_equal(r.final_loss,
+                                                                            r.verify_mean_v))}}
 
 
 def main() -> int:
@@ -518,6 +565,9 @@ def main() -> int:
         print("bench.py measures one GPU: the library has no multi-GPU path (the ensemble would "
               "shard by particles or parameter sets); run with --gpus 1", file=sys.stderr)
         return 2
+
+    # the instruction-mix ceiling, measured in a child process before this one touches the GPU
+    ceiling = mix_ceiling()
 
     import torch
 
@@ -583,12 +633,11 @@ def main() -> int:
     kernel = "k_integrate_" + scheme
     traffic = load_traffic(kernel, args.workload)
     lane_instr = VALU_INSTR_PER_STEP[scheme] * kern_rate
-    # issue time the loop's instruction mix needs at the measured class costs, over the time the
-    # SIMDs actually spent: the share of the VALU issue capacity the kernel uses
-    trips_per_simd = ps / 4 / 64 / N_SIMD
-    model_s = trips_per_simd * sum(c * CLASS_NS[k] for k, c in
-                                   LOOP_CLASS_COUNTS[scheme].items()) * 1e-9
-    issue_util = model_s / (kern_ms * 1e-3)
+    # the same instruction mix replayed without dependencies at full residency (8 wavefronts per
+    # SIMD) sets the ceiling: 4 particle-steps per lane per trip on every lane of every SIMD
+    n_simd = torch.cuda.get_device_properties(dev).multi_processor_count * 4
+    trip_ns = ceiling[scheme][8]
+    ceiling_rate = n_simd * 64 * 4 / (trip_ns * 1e-9)
     trans_rate = TRANS_PER_STEP[scheme] * kern_rate
     trans_peak = N_SIMD * 64 / (TRANS_NS_PER_WAVE_INSTR * 1e-9)
     o = out.cpu()
@@ -617,9 +666,10 @@ def main() -> int:
                      "counted_tflops": COUNTED_FLOP_PER_STEP[scheme] * kern_rate / 1e12,
                      "valu_issue": {"instr_per_particle_step": VALU_INSTR_PER_STEP[scheme],
                                     "lane_instr_per_s": lane_instr,
-                                    "frac_of_one_wave_instr_per_4_cycles":
-                                        lane_instr / VALU_LANE_INSTR_PER_S,
-                                    "class_weighted_utilization": issue_util},
+                                    "mix_ceiling_trip_ns": trip_ns,
+                                    "mix_ceiling_particle_steps_per_s": ceiling_rate,
+                                    "kernel_over_mix_ceiling": kern_rate / ceiling_rate,
+                                    "mix_trip_ns_by_waves_per_simd": ceiling[scheme]},
                      "transcendental": {"per_particle_step": TRANS_PER_STEP[scheme],
                                         "per_s": trans_rate, "peak_per_s": trans_peak,
                                         "frac": trans_rate / trans_peak}},
@@ -632,6 +682,7 @@ def main() -> int:
                                    "single_set": tune_em or "default"}
         line["adjoint"] = adjoint_bench()
         line["adjoint_heun"] = adjoint_bench(scheme="heun")
+        line["adjoint_batched"] = adjoint_batched_item()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, BASE_PARAMS)
     print(json.dumps(line), flush=True)
