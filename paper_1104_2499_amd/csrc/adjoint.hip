@@ -207,11 +207,12 @@ __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
 }
 
 // Values of one sub-window staged for the reverse sweep, per step: cos and sin of the phase
-// 2 pi (x + phi), v and e (the rounded sums the drift saw), sigma xi; for Heun also the same at
-// the predictor point.
+// 2 pi (x + phi), v and e (the rounded sums the drift saw), sigma xi; for Heun also cos and sin at
+// the predictor point (its v and e are recomputed in the reverse sweep from the staged values, by
+// the forward's own expressions, so they carry the forward's bits without taking registers).
 // NB = steps per sub-window, 16 or 8. For Euler-Maruyama 8 stages half the registers, so that two
-// wavefronts fit one SIMD; the Heun kernel holds one wavefront per SIMD either way (~320 VGPRs at
-// 8, the full 512 with a few spilled at 16), and 16 halves the per-window overheads.
+// wavefronts fit one SIMD; the Heun kernel holds one wavefront per SIMD either way (~270 registers
+// at 8, ~460 at 16, no scratch at either), and 16 halves the per-window overheads.
 template <int SCHEME, int NB>
 struct Stage;
 
@@ -224,7 +225,7 @@ struct Stage<0, NB> {
 template <int NB>
 struct Stage<1, NB> {
     static constexpr int B = NB;
-    float c[B], s[B], v[B], e[B], ct[B], st[B], vt[B], et[B], z[B];
+    float c[B], s[B], v[B], e[B], ct[B], st[B], z[B];
 };
 
 // Recompute slot t of a sub-window (absolute step base + t), staging its inputs. The noise is
@@ -250,15 +251,9 @@ __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_
     B.e[t] = ec;
     B.z[t] = zs;
     if constexpr (SCHEME == 1) {
-        float fv0, fe0;
-        drift(k, xc, vc, ec, fv0, fe0);
         const float xp = fmaf(vc, k.dt, xc);
-        const float vp = vc + fmaf(fv0, k.dt, zs);
-        const float ep = fmaf(fe0, k.dt, ec);
         B.ct[t] = __builtin_amdgcn_cosf(xp);
         B.st[t] = __builtin_amdgcn_sinf(xp);
-        B.vt[t] = vp;
-        B.et[t] = ep;
     }
     step<SCHEME>(k, q, xb, zs);
     if ((t & 3) == 3) {
@@ -268,7 +263,8 @@ __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_
 }
 
 // Level 1 over one whole sub-window starting at absolute step base: the same arithmetic as
-// advance(), keeping each sigma*xi in the lane's LDS copy zw[64 t].
+// advance(), keeping each sigma*xi in the lane's LDS copy zw[64 t]. (Computing the next block's
+// noise ahead here, as the forward can, measured slower in this register-heavy kernel.)
 template <int SCHEME, int NB>
 __device__ __forceinline__ void level1_window(const Coef &k, const Stream &s, uint32_t pid,
                                               Particle &p, int64_t base, float *zw)
@@ -389,13 +385,16 @@ __device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc,
     if (CHECK && n + 1 == cx.wb)
         r.lx -= cx.jscale;
     const float h = k.half_dt;
-    const float evt = B.et[t] * B.vt[t], ev = B.e[t] * B.v[t];
+    float fv0, fe0, vt, et;
+    drift_cos(k, B.c[t], B.v[t], B.e[t], fv0, fe0);
+    heun_predictor_ve(k, B.v[t], B.e[t], fv0, fe0, B.z[t], vt, et);
+    const float evt = et * vt, ev = B.e[t] * B.v[t];
     float mx, mv, me;
-    jac_t(k, rc, B.ct[t], B.st[t], B.vt[t], B.et[t], evt, r.lx, r.lv, r.le, mx, mv, me);
+    jac_t(k, rc, B.ct[t], B.st[t], vt, et, evt, r.lx, r.lv, r.le, mx, mv, me);
     const float nx = fmaf(k.dt, mx, r.lx), nv = fmaf(k.dt, mv, r.lv), ne = fmaf(k.dt, me, r.le);
     float px, pv, pe;
     jac_t(k, rc, B.c[t], B.s[t], B.v[t], B.e[t], ev, nx, nv, ne, px, pv, pe);
-    add_terms(r, B.ct[t], B.vt[t], B.et[t], evt, r.lv, r.le);  // times dt/2 at the end
+    add_terms(r, B.ct[t], vt, et, evt, r.lv, r.le);  // times dt/2 at the end
     add_terms(r, B.c[t], B.v[t], B.e[t], ev, nv, ne);
     r.A[2] = fmaf(fmaf(h, mv, r.lv), B.z[t], r.A[2]);
     r.lx = fmaf(h, mx + px, r.lx);
@@ -549,7 +548,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
             put_state(sub + (size_t)(m - m0) * 7 * N, N, L.g, p[0]);
             if constexpr (ZLDS)
                 level1_window<SCHEME, NB>(k, s, pid[0], p[0], m * kStage,
-                                      zl + (size_t)(m - m0) * kStage * 64);
+                                          zl + (size_t)(m - m0) * kStage * 64);
             else
                 advance<SCHEME, 1, 1>(k, s, pid, p, step, (m + 1) * kStage);
         }

@@ -108,13 +108,29 @@ struct Coef {
     float g0, d2, q, c;
 };
 
-__device__ __forceinline__ void drift(const Coef &k, float xs, float v, float e, float &fv,
-                                      float &fe)
+// The drift from c = cos th (the adjoint's reverse sweep re-evaluates it from a staged cosine and
+// gets the forward's bits).
+__device__ __forceinline__ void drift_cos(const Coef &k, float cth, float v, float e, float &fv,
+                                          float &fe)
 {
-    const float cth = __builtin_amdgcn_cosf(xs);
     const float fu = fmaf(-cth, fmaf(k.B, cth, k.K1), k.FH);
     fv = fmaf(fmaf(k.d2, e, -k.g0), v, fu);
     fe = fmaf(-e, fmaf(k.d2 * v, v, k.c), k.q);
+}
+
+__device__ __forceinline__ void drift(const Coef &k, float xs, float v, float e, float &fv,
+                                      float &fe)
+{
+    drift_cos(k, __builtin_amdgcn_cosf(xs), v, e, fv, fe);
+}
+
+// The stochastic Heun predictor's velocity and energy from the drift (fv0, fe0) at the current
+// point: the expressions step_heun uses (the adjoint recomputes them with the same bits).
+__device__ __forceinline__ void heun_predictor_ve(const Coef &k, float vc, float ec, float fv0,
+                                                  float fe0, float zs, float &vp, float &ep)
+{
+    vp = vc + fmaf(fv0, k.dt, zs);
+    ep = fmaf(fe0, k.dt, ec);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -151,8 +167,8 @@ __device__ __forceinline__ void step_heun(const Coef &k, Particle &p, float xb, 
     float fv0, fe0, fv1, fe1;
     drift(k, xc, vc, ec, fv0, fe0);
     const float xp = fmaf(vc, k.dt, xc);
-    const float vp = vc + fmaf(fv0, k.dt, zs);
-    const float ep = fmaf(fe0, k.dt, ec);
+    float vp, ep;
+    heun_predictor_ve(k, vc, ec, fv0, fe0, zs, vp, ep);
     drift(k, xp, vp, ep, fv1, fe1);
     p.lx = fmaf(vc + vp, k.half_dt, p.lx);
     p.lv = p.lv + fmaf(fv0 + fv1, k.half_dt, zs);
