@@ -32,19 +32,18 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # drift, and half a Box-Muller pair (5 per pair). Transcendentals are counted separately.
 FLOP_PER_STEP = dict(em=24, heun=48)
 TRANS_PER_STEP = dict(em=3, heun=4)
-# VALU instructions per particle-step in the hot loop of k_integrate<scheme, 1, 1> (gfx950 ISA,
-# one Philox block = 4 steps per loop trip: EM 128, Heun 188; SQ_INSTS_VALU of a profiled run
-# gives 128.04 and 188.03 per block).
-VALU_INSTR_PER_STEP = dict(em=128 / 4, heun=188 / 4)
+# VALU instructions per particle-step in the hot loop of k_integrate<scheme, 1, 1> (gfx950 ISA, one
+# aligned 8-step span = two Philox blocks per loop trip: EM 241, Heun 361).
+VALU_INSTR_PER_STEP = dict(em=241 / 8, heun=361 / 8)
 # FP32 FLOPs per particle-step as the hardware counts them (SQ_INSTS_VALU_FLOPS_FP32: FMA = 2,
-# add, mul and transcendental = 1), including the high/low bookkeeping and Box-Muller: Heun
-# measured (equal to the ISA's 72 FMA, 45 add, 14 mul, 16 transcendental per block); EM from its
-# ISA by the same rule (36 FMA, 29 add, 10 mul, 12 transcendental per block).
-COUNTED_FLOP_PER_STEP = dict(em=30.75, heun=54.75)
+# add, mul and transcendental = 1), including the high/low bookkeeping and Box-Muller, from the
+# same loops: Heun 144 FMA, 79 add/sub, 28 mul, 32 transcendental per span; EM 72, 47, 20, 24.
+COUNTED_FLOP_PER_STEP = dict(em=235 / 8, heun=427 / 8)
 # Issue time of v_cos/v_sin/v_log/v_sqrt_f32 per wave64 instruction per SIMD, measured by
 # ubench/valu_rates.hip (profiles/valu_issue_rates.txt).
 TRANS_NS_PER_WAVE_INSTR = 3.45
 UBENCH = os.path.join(ROOT, "paper_1104_2499_amd", "ubench", "valu_rates")
+STEPS_PER_TRIP = 8  # one loop trip of k_integrate: an aligned 8-step span
 
 
 def mix_ceiling() -> dict:
@@ -634,10 +633,10 @@ def main() -> int:
     traffic = load_traffic(kernel, args.workload)
     lane_instr = VALU_INSTR_PER_STEP[scheme] * kern_rate
     # the same instruction mix replayed without dependencies at full residency (8 wavefronts per
-    # SIMD) sets the ceiling: 4 particle-steps per lane per trip on every lane of every SIMD
+    # SIMD) sets the ceiling: 8 particle-steps per lane per trip on every lane of every SIMD
     n_simd = torch.cuda.get_device_properties(dev).multi_processor_count * 4
     trip_ns = ceiling[scheme][8]
-    ceiling_rate = n_simd * 64 * 4 / (trip_ns * 1e-9)
+    ceiling_rate = n_simd * 64 * STEPS_PER_TRIP / (trip_ns * 1e-9)
     trans_rate = TRANS_PER_STEP[scheme] * kern_rate
     trans_peak = N_SIMD * 64 / (TRANS_NS_PER_WAVE_INSTR * 1e-9)
     o = out.cpu()

@@ -94,7 +94,7 @@ typedef struct abp_run {
 /* Particle state in structure-of-arrays form, device memory. Sec. 2 of the paper asks single
  * precision to avoid adding very small numbers to very big ones; the state is therefore kept as
  * FP32 high/low pairs: x = cell + xf + lx with an integer cell, v = v + lv, e = e + le. The
- * integrator keeps xf in [-1/2, 1/2] (it moves the nearest integer into the cell every four
+ * integrator keeps xf in [-1/2, 1/2] (it moves the nearest integer into the cell every eight
  * steps, exactly while |xf| < 2^23; the initial state has xf in [0, 1)). d_lo holds 3n floats:
  * lx at [0, n), lv at [n, 2n), le at [2n, 3n). The low parts are part of the state (a run split
  * into calls is bit-identical to one call only if they are carried). Particle i has Philox id

@@ -18,7 +18,7 @@
 // lanes x 4 bytes per wavefront; one four-wavefront block per CU with 16-step staging, two with
 // 8-step staging), level 1 keeps each sigma*xi it draws there and the staged recomputation reads
 // it back instead of running Philox and Box-Muller a second time. The recomputation reproduces
-// the forward bits exactly (the integrator's state is resumable mid-block), so the result does
+// the forward bits exactly (the integrator's state is resumable mid-span), so the result does
 // not depend on K. Per-step gradient terms are summed in FP32 within each absolute B-step window
 // and in FP64 across windows (that grouping does not depend on K either); tiles of 64 particles
 // and sets are then reduced in a fixed order.
@@ -256,8 +256,8 @@ __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_
         B.st[t] = __builtin_amdgcn_sinf(xp);
     }
     step<SCHEME>(k, q, xb, zs);
-    if ((t & 3) == 3) {
-        end_block(q);
+    if ((t & (kSpan - 1)) == kSpan - 1) {
+        end_span(q);
         xb = q.xf + k.phi;
     }
 }
@@ -269,17 +269,17 @@ template <int SCHEME, int NB>
 __device__ __forceinline__ void level1_window(const Coef &k, const Stream &s, uint32_t pid,
                                               Particle &p, int64_t base, float *zw)
 {
-    constexpr int kB = NB;
 #pragma unroll
-    for (int b = 0; b < kB / 4; ++b) {
-        const Noise4 z = noise_block((uint32_t)((base >> 2) + b), pid, s.set, s.k0, s.k1, k.bm);
-        const float xb = p.xf + k.phi;
+    for (int b = 0; b < NB / kSpan; ++b) {
+        const uint32_t blk = (uint32_t)(base >> 2) + 2 * b;
+        const Noise4 z0 = noise_block(blk, pid, s.set, s.k0, s.k1, k.bm);
+        const Noise4 z1 = noise_block(blk + 1, pid, s.set, s.k0, s.k1, k.bm);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            zw[64 * (4 * b + j)] = z.z[j];
-            step<SCHEME>(k, p, xb, z.z[j]);
+            zw[64 * (kSpan * b + j)] = z0.z[j];
+            zw[64 * (kSpan * b + 4 + j)] = z1.z[j];
         }
-        end_block(p);
+        span_steps<SCHEME>(k, p, z0, z1);
     }
 }
 

@@ -136,11 +136,12 @@ __device__ __forceinline__ void heun_predictor_ve(const Coef &k, float vc, float
 // ---------------------------------------------------------------------------------------------
 // Particle state as a float-float pair per coordinate (the single-precision remedy for adding
 // small increments to large values): x = cell + xf + lx, v = v + lv, e = e + le.
-// Within an aligned block of four steps the high parts (cell, xf, v, e) stay fixed and every
-// increment goes into the low part, which starts the block holding the previous rounding error;
-// after the block's last step each pair is renormalised by Fast2Sum (exact whenever the high part
-// is the larger) and the nearest integer of xf moves into the cell, exactly. The drift sees the
-// rounded sums (high + low). A state stored mid-block is resumed bit for bit.
+// Within an aligned span of kSpan = 8 steps (two noise blocks) the high parts (cell, xf, v, e) stay
+// fixed and every increment goes into the low part, which starts the span holding the previous
+// rounding error; after the span's last step each pair is renormalised by Fast2Sum (exact
+// whenever the high part is the larger) and the nearest integer of xf moves into the cell,
+// exactly. The drift sees the rounded sums (high + low). A state stored mid-span is resumed bit
+// for bit.
 // ---------------------------------------------------------------------------------------------
 struct Particle {
     int32_t cell;
@@ -191,12 +192,17 @@ __device__ __forceinline__ void renorm(float &hi, float &lo)
     hi = t;
 }
 
-// End of an aligned block (after absolute step 4b+3): renormalise the pairs, then move the nearest
+// Steps between renormalisations: two noise blocks. (The low parts then hold at most eight
+// increments; the span end's fixed cost -- three Fast2Sums, the wrap, the phase -- is paid once per
+// eight steps.)
+constexpr int kSpan = 8;
+
+// End of an aligned span (after absolute step 8b+7): renormalise the pairs, then move the nearest
 // integer of xf into the cell, leaving xf in [-1/2, 1/2]. For a binary float |x| < 2^23 the
 // difference x - rint(x) is exactly representable (it keeps bits of x below the units place), so
 // the wrap loses nothing and needs no error term. x leaves [-1/2, 1/2] by at most a few |v| dt per
-// block, and cos (in revolutions) is periodic.
-__device__ __forceinline__ void end_block(Particle &p)
+// span, and cos (in revolutions) is periodic.
+__device__ __forceinline__ void end_span(Particle &p)
 {
     renorm(p.xf, p.lx);
     renorm(p.v, p.lv);
@@ -217,109 +223,128 @@ struct Stream {
     uint32_t set;
 };
 
-// One aligned block of four steps of one particle with the block's noise z, then the block end.
+// One aligned span of eight steps of one particle with the noise of its two blocks, then the span
+// end.
 template <int SCHEME>
-__device__ __forceinline__ void block_steps(const Coef &k, Particle &p, const Noise4 &z)
+__device__ __forceinline__ void span_steps(const Coef &k, Particle &p, const Noise4 &z0,
+                                           const Noise4 &z1)
 {
     const float xb = p.xf + k.phi;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-        step<SCHEME>(k, p, xb, z.z[j]);
-    end_block(p);
+        step<SCHEME>(k, p, xb, z0.z[j]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        step<SCHEME>(k, p, xb, z1.z[j]);
+    end_span(p);
+}
+
+// Steps n .. lim-1 of one particle, one at a time, all inside one span (lim <= the span's end):
+// each noise block is drawn as it is entered, and the span ends if lim closes it.
+template <int SCHEME>
+__device__ __forceinline__ void partial_steps(const Coef &k, const Stream &s, uint32_t pid,
+                                              Particle &p, int64_t n, int64_t lim)
+{
+    const float xb = p.xf + k.phi;
+    Noise4 z = noise_block((uint32_t)(n >> 2), pid, s.set, s.k0, s.k1, k.bm);
+    for (int64_t m = n; m < lim; ++m) {
+        if ((m & 3) == 0 && m != n)
+            z = noise_block((uint32_t)(m >> 2), pid, s.set, s.k0, s.k1, k.bm);
+        step<SCHEME>(k, p, xb, pick(z, (uint32_t)(m & 3)));
+    }
+    if ((lim & (kSpan - 1)) == 0)
+        end_span(p);
 }
 
 // Advance PPL particles of one lane from absolute step n to `stop` (both wavefront-uniform).
-// Blocks of four steps aligned on absolute indices take the fast path; a call that starts or
-// ends inside a block handles its partial block step by step. Block ends (renormalisation and
-// wrap) happen only after absolute steps 4b+3, so any split of a run into calls gives
-// bit-identical states.
-// Loop forms (all compute the same values): LOOP = 1, each block's noise right before its steps;
-// LOOP = 2, two blocks' noise per loop trip, then their steps; LOOP = kAhead, the noise of block
-// b+1 (Philox and Box-Muller, which do not depend on the state) computed while block b steps, so
+// Spans of eight steps aligned on absolute indices take the fast path; a call that starts or ends
+// inside a span handles its partial span step by step. Span ends (renormalisation and wrap)
+// happen only after absolute steps 8b+7, so any split of a run into calls gives bit-identical
+// states.
+// Loop forms (all compute the same values): LOOP = 1, each span's noise right before its steps;
+// LOOP = 2, two spans' noise per loop trip, then their steps; LOOP = kAhead, the noise of span
+// b+1 (Philox and Box-Muller, which do not depend on the state) computed while span b steps, so
 // that the two dependency chains overlap in one instruction stream -- for launches that hold one
 // or two wavefronts per SIMD, where a wavefront's own instruction stream is all the SIMD has.
+// Loop counters are 32-bit (spans of one call < 2^31), so that loop control stays scalar.
 constexpr int kAhead = 3;
 
 template <int SCHEME, int PPL, int UNROLL>
 __device__ __forceinline__ void advance(const Coef &k, const Stream &s, const uint32_t (&pid)[PPL],
                                         Particle (&p)[PPL], int64_t &n, int64_t stop)
 {
-    // leading partial block
-    if (n < stop && (n & 3)) {
-        const uint32_t blk = (uint32_t)(n >> 2);
-        const uint32_t j0 = (uint32_t)(n & 3);
-        const uint32_t j1 = (uint32_t)((stop - n) < (int64_t)(4 - j0) ? j0 + (stop - n) : 4);
+    // leading partial span
+    if (n < stop && (n & (kSpan - 1))) {
+        const int64_t end = (n | (kSpan - 1)) + 1;
+        const int64_t lim = stop < end ? stop : end;
 #pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
-            const float xb = p[q].xf + k.phi;
-            for (uint32_t j = j0; j < j1; ++j)
-                step<SCHEME>(k, p[q], xb, pick(z, j));
-            if (j1 == 4)
-                end_block(p[q]);
-        }
-        n += (int64_t)(j1 - j0);
+        for (int q = 0; q < PPL; ++q)
+            partial_steps<SCHEME>(k, s, pid[q], p[q], n, lim);
+        n = lim;
     }
-    // aligned blocks
-    const int64_t nblk = (stop - n) >> 2;
+    // aligned spans
+    const uint32_t nsp = (uint32_t)((stop - n) >> 3);
     uint32_t blk = (uint32_t)(n >> 2);
     if constexpr (UNROLL == kAhead) {
-        if (nblk > 0) {
-            Noise4 z[PPL];
+        if (nsp > 0) {
+            Noise4 z0[PPL], z1[PPL];
 #pragma unroll
-            for (int q = 0; q < PPL; ++q)
-                z[q] = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
-            for (int64_t b = 1; b < nblk; ++b) {
-                Noise4 zn[PPL];
-#pragma unroll
-                for (int q = 0; q < PPL; ++q)
-                    zn[q] = noise_block(blk + 1, pid[q], s.set, s.k0, s.k1, k.bm);
+            for (int q = 0; q < PPL; ++q) {
+                z0[q] = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
+                z1[q] = noise_block(blk + 1, pid[q], s.set, s.k0, s.k1, k.bm);
+            }
+            for (uint32_t b = 1; b < nsp; ++b) {
+                Noise4 n0[PPL], n1[PPL];
 #pragma unroll
                 for (int q = 0; q < PPL; ++q) {
-                    block_steps<SCHEME>(k, p[q], z[q]);
-                    z[q] = zn[q];
+                    n0[q] = noise_block(blk + 2, pid[q], s.set, s.k0, s.k1, k.bm);
+                    n1[q] = noise_block(blk + 3, pid[q], s.set, s.k0, s.k1, k.bm);
                 }
-                ++blk;
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) {
+                    span_steps<SCHEME>(k, p[q], z0[q], z1[q]);
+                    z0[q] = n0[q];
+                    z1[q] = n1[q];
+                }
+                blk += 2;
             }
-            // the last aligned block (a trailing partial block draws its own noise)
+            // the last aligned span (a trailing partial span draws its own noise)
 #pragma unroll
             for (int q = 0; q < PPL; ++q)
-                block_steps<SCHEME>(k, p[q], z[q]);
-            ++blk;
+                span_steps<SCHEME>(k, p[q], z0[q], z1[q]);
+            blk += 2;
         }
     } else {
-        int64_t b = 0;
-        for (; b + UNROLL <= nblk; b += UNROLL) {
+        uint32_t b = 0;
+        for (; b + UNROLL <= nsp; b += UNROLL) {
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
 #pragma unroll
                 for (int q = 0; q < PPL; ++q) {
-                    const Noise4 z = noise_block(blk + u, pid[q], s.set, s.k0, s.k1, k.bm);
-                    block_steps<SCHEME>(k, p[q], z);
+                    const Noise4 z0 = noise_block(blk + 2 * u, pid[q], s.set, s.k0, s.k1, k.bm);
+                    const Noise4 z1 =
+                        noise_block(blk + 2 * u + 1, pid[q], s.set, s.k0, s.k1, k.bm);
+                    span_steps<SCHEME>(k, p[q], z0, z1);
                 }
             }
-            blk += UNROLL;
+            blk += 2 * UNROLL;
         }
-        for (; b < nblk; ++b) {
+        for (; b < nsp; ++b) {
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
-                const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
-                block_steps<SCHEME>(k, p[q], z);
+                const Noise4 z0 = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
+                const Noise4 z1 = noise_block(blk + 1, pid[q], s.set, s.k0, s.k1, k.bm);
+                span_steps<SCHEME>(k, p[q], z0, z1);
             }
-            ++blk;
+            blk += 2;
         }
     }
-    n += nblk << 2;
-    // trailing partial block (its end is taken by the call that finishes the block)
+    n += (int64_t)nsp << 3;
+    // trailing partial span (its end is taken by the call that finishes the span)
     if (n < stop) {
-        const uint32_t j1 = (uint32_t)(stop - n);
 #pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-            const Noise4 z = noise_block(blk, pid[q], s.set, s.k0, s.k1, k.bm);
-            const float xb = p[q].xf + k.phi;
-            for (uint32_t j = 0; j < j1; ++j)
-                step<SCHEME>(k, p[q], xb, pick(z, j));
-        }
+        for (int q = 0; q < PPL; ++q)
+            partial_steps<SCHEME>(k, s, pid[q], p[q], n, stop);
         n = stop;
     }
 }

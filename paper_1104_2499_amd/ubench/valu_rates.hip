@@ -101,25 +101,30 @@ __global__ __launch_bounds__(256) void k_rate(float *out, float seedf, uint32_t 
 
 // ---------------------------------------------------------------------------------------------
 // The integrators' own instruction mix, replayed without dependencies: the measured ceiling of
-// that mix. Each string is the instruction sequence of one 4-step loop trip of k_integrate (one
-// particle per lane, in-place noise loop), in program order as hipcc -O3 compiles it for gfx950,
-// one letter per instruction:
+// that mix. Each string is the instruction sequence of one loop trip of k_integrate -- one aligned
+// 8-step span, two noise blocks, one particle per lane, in-place noise loop -- in program order as
+// hipcc -O3 compiles it for gfx950, one letter per instruction:
 //   F v_fma/v_fmac_f32 with an SGPR operand    G v_fma/v_fmac_f32 on three VGPRs
 //   A v_add/v_sub_f32     M v_mul_f32 with an SGPR    N v_mul_f32 on two VGPRs
 //   C v_cos_f32   S v_sin_f32   L v_log_f32   Q v_sqrt_f32
 //   D v_mad_u64_u32   X v_bitop3_b32   x v_xor_b32   B v_alignbit_b32   V v_mov (32 or 64 bit)
-//   R v_rndne_f32   I v_cvt_i32_f32   U v_add_u32   K v_cmp_ge_i64   s a scalar ALU instruction
+//   R v_rndne_f32   I v_cvt_i32_f32   U v_add_u32 / v_add_co_u32   K v_cmp_ge_i64
+//   s a scalar ALU instruction
 // (tests/test_isa_constraints.py checks that the class counts still match the library's loops).
 // k_mix issues the same sequence on register chains that never wait for each other (each class
 // rotates over a few registers), so its time per trip is the issue cost of the mix alone.
 // ---------------------------------------------------------------------------------------------
 static constexpr char kHeunTrip[] =
-    "ssVAssVAAssxCMFssDAFCsxsFDsXxFDDFFFXXGFDDXXDDXXDDXXDDXXDDXXBDXBALBALBMCQSMCSQNFN"
-    "FFANNGMAFFAFFAAACFAFCAMFFFFFGFFFFAFGMAFFAFFAAACFAFCAMFFFFFGFFFFAFGMAFFAFFAAACFAF"
-    "CAMFFFFFGFFFFAFGMAFFAFFAAARFIsAAsAAAAsAAsAUsssVKs";
+    "sssssssVVAsssxAAssssDCMsxAFFssxDsCsFsDsxsXxDsFDDXxFFXXDDFGDDXXFXXDDDDXXXXDDDDXXX"
+    "XDDDDXXXXDDDDXXXXDDDBXXXBADBBXAABLLALLBMMCSCBQQMCSQBMCSSQNNNFNNFFANNNGMAFFAFFAAA"
+    "CFAFCAMFFFFFGFFFFAFGMAFFAFFAAACFAFCAMFFFFFGFFFFAFGMAFFAFFAAACFAFCAMFFFFFGFFFFAFG"
+    "MAFFAFFAAACFAFCAMFFFFFGFFFFAFGMAFFAFFAAACFAFCAMFFFFFGFFFFAFGMAFFAFFAAACFAFCAMFFF"
+    "FFGFFFFAFGMAFFAFFAAACFAFCAMFFFFFGFFFFAFGAMFAFFAFARAAAIAFAAUAAssAAUs";
 static constexpr char kEmTrip[] =
-    "ssVAssAAssxVCMsDAFsFxFAsFDsCsXxFDDFXXFFDDGFXXDDXXDDXXDDXXDDXXBDXBALBCBMQASLNFAAF"
-    "MNACSQGMFFFAFACFANNMFAFAFFFCFGFFAAFFAFGMFFFAFAARAIsFAsAAAsAAsAUsssVKs";
+    "sssssVssxVsAAsDsAsMsAsCxFxFFsssDFDAssssCsxXxsFDsFDDXxFXXDDGDDFXXXXFDDDDXXXXDDDDX"
+    "XXXDDDDXXXXDDDDXXXXDDDBXXXBADBBXAALLBABLMMCSCQQBMSLCSQNNNFAAFABMNNNGMFCSQFFAFACF"
+    "AMFNNAFAFFFCFGFFAAFFAFGMFFFAFACFAMFAFAFFFCFGFFAAFFAFGMFFFAFACFAFAAMFCFFFFGFFAAFF"
+    "AFGMFFFAFARAAIAFAAUAAssAAUs";
 
 constexpr char trip_op(int kind, int i) { return kind == 0 ? kHeunTrip[i] : kEmTrip[i]; }
 constexpr int trip_len(int kind) { return kind == 0 ? (int)sizeof(kHeunTrip) - 1 : (int)sizeof(kEmTrip) - 1; }
@@ -354,7 +359,7 @@ int main(int argc, char **argv)
                 prop.gcnArchName, cus, prop.clockRate, CHAINS, ITERS);
     if (!mix_only)
         class_rates(prop, d_out);
-    // the integrators' instruction mix: time per 4-step trip per wave per SIMD, by residency
+    // the integrators' instruction mix: time per 8-step trip per wave per SIMD, by residency
     const int mix_iters = 1024;
     for (int kind = 0; kind < 2; ++kind) {
         const char *name = kind == 0 ? "heun" : "em";
