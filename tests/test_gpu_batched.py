@@ -177,3 +177,25 @@ def test_autotuner_picks_a_shape_that_changes_no_bits(gpu, tmp_path, monkeypatch
     s2 = api.sweep(table, n_traj, n_steps, window, scheme="em", bins=16)
     np.testing.assert_array_equal(s1.mean_v, s2.mean_v)
     assert torch.equal(s1.hist, s2.hist)
+
+
+def test_many_small_sets_planned_on_the_device(gpu):
+    """50000 sets of 1-70 particles and 2-40 steps in one launch: the device-side plan ranks sets
+    across many blocks (step counts tie constantly; ties go in set order) and scans offsets over
+    49 chunks of its scan block. Every histogram holds its set's particles, and sampled sets equal
+    their single runs bit for bit."""
+    from paper_1104_2499_amd import api
+    from paper_1104_2499_amd.workloads import sweep_table
+
+    rng = np.random.default_rng(8)
+    n_sets = 50_000
+    table, _, _ = sweep_table(n_sets, seed=8)
+    n_traj = rng.integers(1, 71, n_sets).astype(np.int32)
+    n_steps = rng.integers(2, 41, n_sets).astype(np.int64)
+    r = api.sweep(table, n_traj, n_steps, scheme="em", seed=19, bins=16)
+    np.testing.assert_array_equal(r.hist.sum(dim=1).cpu().numpy(), n_traj)
+    assert np.all(np.isfinite(r.mean_v))
+    for k in [0, n_sets - 1, *rng.choice(n_sets, 10, replace=False).tolist()]:
+        a = _alone(k, table, n_traj, n_steps, n_steps // 2, "em", 19, 16)
+        assert r.mean_v[k] == a.mean_v and r.stderr[k] == a.stderr, k
+        assert torch.equal(r.hist[k], a.hist), k
