@@ -14,10 +14,12 @@
 // multiple of 16). Then, for each sub-window in reverse, it restores the sub-checkpoint,
 // recomputes the sub-window while staging the values the reverse step needs (cos and sin of the
 // phase, v, e at every point where the drift is evaluated, and sigma*xi) in registers, and runs
-// the adjoint recursion backwards over it. When the segment's noise fits in LDS (K - B steps x 64
+// the adjoint recursion backwards over it. When the segment's noise fits in LDS (K steps x 64
 // lanes x 4 bytes per wavefront; one four-wavefront block per CU with 16-step staging, two with
 // 8-step staging), level 1 keeps each sigma*xi it draws there and the staged recomputation reads
-// it back instead of running Philox and Box-Muller a second time. The recomputation reproduces
+// it back instead of running Philox and Box-Muller a second time. For Heun the last sub-window's
+// noise (drawn by its staged recomputation) is kept too, K steps in all, and the reverse steps
+// read it there instead of from registers; Euler-Maruyama keeps K - B steps. The recomputation reproduces
 // the forward bits exactly (the integrator's state is resumable mid-span), so the result does
 // not depend on K. Per-step gradient terms are summed in FP32 within each absolute B-step window
 // and in FP64 across windows (that grouping does not depend on K either); tiles of 64 particles
@@ -42,7 +44,7 @@ struct RevCoef {
     float four_pi_U0;  // 4 pi U0             (dU'/da  = 4 pi U0 cos 2th)
     float a2;          // 2a
     float eight_a;     // 8a                  (U'' = -4 pi^2 U0 sin th (1 + 8a cos th))
-    float m4pi2U0;     // -4 pi^2 U0
+    float m4pi2U0_h;   // -4 pi^2 U0 dt/2     (the Heun corrector's weight on U'')
     float inv2D;       // 1 / (2D)            (d(sigma xi)/dD = sigma xi / (2D))
     // the Euler-Maruyama reverse step runs on Lam = dt lam, with the step's dt folded in here
     float m4pi2U0_dt;  // -4 pi^2 U0 dt
@@ -75,7 +77,7 @@ struct AdjArgs {
     int32_t n_sets;
     float rho;        // per-step decay of the adjoint (1 = exact gradient)
     int32_t vform;    // 1: the loss enters as (1/W) sum of v_n over the window (used with rho < 1)
-    int32_t z_slots;  // steps of noise each lane keeps in LDS (K - B), when that variant runs
+    int32_t z_slots;  // steps of noise each lane keeps in LDS (Heun K, Euler-Maruyama K - B)
 };
 
 constexpr int kAlign = 16;    // checkpoint intervals are multiples of this
@@ -141,7 +143,9 @@ __device__ __forceinline__ Particle get_state(const float *base, int64_t N, int6
     return p;
 }
 
-// The lane's place: wave w of the grid covers tile (w mod tiles) of set (w / tiles).
+// The lane's place: wave w of the grid covers tile (w mod tiles) of set (w / tiles). The wave
+// index is taken from the first lane, so that set and tile are known to be wavefront-uniform
+// (scalar registers, and scalar loads of the set's row).
 struct Lane {
     int lane;
     int32_t set;
@@ -152,7 +156,8 @@ struct Lane {
 __device__ __forceinline__ bool locate(const AdjArgs &a, Lane &L)
 {
     L.lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                         __builtin_amdgcn_readfirstlane((uint32_t)threadIdx.x >> 6);
     if (wave >= (int64_t)a.n_sets * a.tiles)
         return false;  // wavefront-uniform
     L.set = (int32_t)(wave / a.tiles);
@@ -177,12 +182,13 @@ __device__ __forceinline__ Particle initial_particle(uint32_t pid, uint32_t set,
 
 // Forward phase: integrate, store a checkpoint at every multiple of K, reduce the loss.
 template <int SCHEME, int LOOP>
-__global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
+__global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a, const AdjRow *__restrict__ rows)
 {
     Lane L;
     if (*a.status != ABP_OK || !locate(a, L))
         return;
-    const AdjRow &row = a.rows[L.set];
+    // the set's row by value (scalar registers): read once, whatever the kernel stores
+    const AdjRow row = rows[L.set];
     const Stream s{a.k0, a.k1, (uint32_t)L.set};
     const uint32_t pid[1] = {(uint32_t)L.i};
     Particle p[1] = {initial_particle(pid[0], (uint32_t)L.set, a.k0, a.k1)};
@@ -207,12 +213,11 @@ __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a)
 }
 
 // Values of one sub-window staged for the reverse sweep, per step: cos and sin of the phase
-// 2 pi (x + phi), v and e (the rounded sums the drift saw), sigma xi; for Heun also cos and sin at
-// the predictor point (its v and e are recomputed in the reverse sweep from the staged values, by
-// the forward's own expressions, so they carry the forward's bits without taking registers).
+// 2 pi (x + phi), v and e (the rounded sums the drift saw), sigma xi; for Heun also cos, sin, v and
+// e at the predictor point (the values the step's second drift saw).
 // NB = steps per sub-window, 16 or 8. For Euler-Maruyama 8 stages half the registers, so that two
-// wavefronts fit one SIMD; the Heun kernel holds one wavefront per SIMD either way (~270 registers
-// at 8, ~460 at 16, no scratch at either), and 16 halves the per-window overheads.
+// wavefronts fit one SIMD; the Heun kernel holds one wavefront per SIMD either way, and 16 halves
+// the per-window overheads.
 template <int SCHEME, int NB>
 struct Stage;
 
@@ -225,16 +230,17 @@ struct Stage<0, NB> {
 template <int NB>
 struct Stage<1, NB> {
     static constexpr int B = NB;
-    float c[B], s[B], v[B], e[B], ct[B], st[B], z[B];
+    float c[B], s[B], v[B], e[B], ct[B], st[B], vt[B], et[B], z[B];
 };
 
 // Recompute slot t of a sub-window (absolute step base + t), staging its inputs. The noise is
-// regenerated or (FROM_LDS) read from the lane's LDS copy zl[64 t] kept by level 1. The staged
-// predictor repeats step_heun's own expressions, so it holds the values that step saw.
+// regenerated or (FROM_LDS) read from the lane's LDS copy zl[64 t] kept by level 1; regenerated
+// noise is also kept there when zl is given. The staged predictor repeats step_heun's own
+// expressions (the compiler merges the two), so it holds the values that step saw.
 template <int SCHEME, bool FROM_LDS, class ST>
 __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_t pid, Particle &q,
                                          float &xb, Noise4 &z, int64_t base, int t, ST &B,
-                                         const float *zl)
+                                         float *zl)
 {
     float zs;
     if constexpr (FROM_LDS) {
@@ -243,6 +249,8 @@ __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_
         if ((t & 3) == 0)
             z = noise_block((uint32_t)((base + t) >> 2), pid, s.set, s.k0, s.k1, k.bm);
         zs = z.z[t & 3];
+        if (zl)
+            zl[64 * t] = zs;
     }
     const float xc = xb + q.lx, vc = q.v + q.lv, ec = q.e + q.le;
     B.c[t] = __builtin_amdgcn_cosf(xc);
@@ -254,6 +262,9 @@ __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_
         const float xp = fmaf(vc, k.dt, xc);
         B.ct[t] = __builtin_amdgcn_cosf(xp);
         B.st[t] = __builtin_amdgcn_sinf(xp);
+        float fv0, fe0;
+        drift(k, xc, vc, ec, fv0, fe0);
+        heun_predictor_ve(k, vc, ec, fv0, fe0, zs, B.vt[t], B.et[t]);
     }
     step<SCHEME>(k, q, xb, zs);
     if ((t & (kSpan - 1)) == kSpan - 1) {
@@ -311,7 +322,7 @@ struct RevCtx {
 // lam_n = lam' + dt J(y)^T lam'.
 template <int VFORM, bool CHECK, int NB>
 __device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc,
-                                            const Stage<0, NB> &B, int t, int64_t n,
+                                            const Stage<0, NB> &B, int t, float z, int64_t n,
                                             const RevCtx &cx, float add_w, Rev &r)
 {
     if (CHECK && !VFORM && n + 1 == cx.wb)
@@ -322,7 +333,7 @@ __device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc,
     const float wc = r.lv * c;
     r.A[0] += wc;
     r.A[1] = fmaf(wc, c, r.A[1]);
-    r.A[2] = fmaf(r.lv, B.z[t], r.A[2]);
+    r.A[2] = fmaf(r.lv, z, r.A[2]);
     r.A[3] = fmaf(r.lv, ev, r.A[3]);
     r.A[4] = fmaf(lev, v, r.A[4]);
     r.A[5] += r.le;
@@ -351,85 +362,103 @@ __device__ __forceinline__ void rev_slot_em(const Coef &k, const RevCoef &rc,
 //   mu = J(yp)^T lam',  nu = lam' + dt mu,  lam_n = lam' + dt/2 (mu + J(y)^T nu);
 // the parameter terms are dt/2 f_theta(yp)^T lam' + dt/2 f_theta(y)^T nu, and sigma enters
 // through both the corrector and the predictor: (lam'_v + dt/2 mu_v) xi.
-// J(y)^T w at a drift point with cos c, sin sn, v, e and ev = e v.
+// J(y)^T w at a drift point with cos c, sin sn, v, e and ev = e v. The x component, -U''(x) w_v,
+// is returned divided by 4 pi^2 U0 (the caller applies that constant together with the step's dt
+// or dt/2, from the row), and we_ev = w_e e v, which the d2 term of the parameter sums shares.
 __device__ __forceinline__ void jac_t(const Coef &k, const RevCoef &rc, float c, float sn, float v,
                                       float e, float ev, float wx, float wv, float we, float &ox,
-                                      float &ov, float &oe)
+                                      float &ov, float &oe, float &we_ev)
 {
-    const float upp = rc.m4pi2U0 * (sn * fmaf(rc.eight_a, c, 1.0f));  // U''(x)
+    ox = (sn * fmaf(rc.eight_a, c, 1.0f)) * wv;  // U''(x) w_v / (-4 pi^2 U0)
     const float d2v = k.d2 * v;
-    ox = -upp * wv;
-    ov = fmaf((-2.0f * k.d2) * we, ev, fmaf(fmaf(k.d2, e, -k.g0), wv, wx));
+    we_ev = we * ev;
+    ov = fmaf(-2.0f * k.d2, we_ev, fmaf(fmaf(k.d2, e, -k.g0), wv, wx));
     oe = fmaf(d2v, wv, -fmaf(d2v, v, k.c) * we);
 }
 
 __device__ __forceinline__ void add_terms(Rev &r, float c, float v, float e, float ev, float wv,
-                                          float we)
+                                          float we, float we_ev)
 {
     const float wc = wv * c;
     r.A[0] += wc;
     r.A[1] = fmaf(wc, c, r.A[1]);
     r.A[3] = fmaf(wv, ev, r.A[3]);
-    r.A[4] = fmaf(we * ev, v, r.A[4]);
+    r.A[4] = fmaf(we_ev, v, r.A[4]);
     r.A[5] += we;
     r.A[6] = fmaf(we, e, r.A[6]);
     r.A[7] = fmaf(wv, v, r.A[7]);
     r.A[8] += wv;
 }
 
-template <bool CHECK, int NB>
+// PRED: the predictor's v and e come from the stage; otherwise they are recomputed here from the
+// staged values by the forward's own expressions (the same bits, in fewer registers).
+template <bool CHECK, bool PRED, int NB>
 __device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc,
-                                              const Stage<1, NB> &B, int t, int64_t n,
+                                              const Stage<1, NB> &B, int t, float z, int64_t n,
                                               const RevCtx &cx, Rev &r)
 {
     if (CHECK && n + 1 == cx.wb)
         r.lx -= cx.jscale;
     const float h = k.half_dt;
-    float fv0, fe0, vt, et;
-    drift_cos(k, B.c[t], B.v[t], B.e[t], fv0, fe0);
-    heun_predictor_ve(k, B.v[t], B.e[t], fv0, fe0, B.z[t], vt, et);
+    float vt, et;
+    if constexpr (PRED) {
+        vt = B.vt[t];
+        et = B.et[t];
+    } else {
+        float fv0, fe0;
+        drift_cos(k, B.c[t], B.v[t], B.e[t], fv0, fe0);
+        heun_predictor_ve(k, B.v[t], B.e[t], fv0, fe0, z, vt, et);
+    }
     const float evt = et * vt, ev = B.e[t] * B.v[t];
-    float mx, mv, me;
-    jac_t(k, rc, B.ct[t], B.st[t], vt, et, evt, r.lx, r.lv, r.le, mx, mv, me);
-    const float nx = fmaf(k.dt, mx, r.lx), nv = fmaf(k.dt, mv, r.lv), ne = fmaf(k.dt, me, r.le);
-    float px, pv, pe;
-    jac_t(k, rc, B.c[t], B.s[t], B.v[t], B.e[t], ev, nx, nv, ne, px, pv, pe);
-    add_terms(r, B.ct[t], vt, et, evt, r.lv, r.le);  // times dt/2 at the end
-    add_terms(r, B.c[t], B.v[t], B.e[t], ev, nv, ne);
-    r.A[2] = fmaf(fmaf(h, mv, r.lv), B.z[t], r.A[2]);
-    r.lx = fmaf(h, mx + px, r.lx);
+    float mx, mv, me, tp;
+    jac_t(k, rc, B.ct[t], B.st[t], vt, et, evt, r.lx, r.lv, r.le, mx, mv, me, tp);
+    // nu = lam' + dt mu (mu_x = 4 pi^2 U0 mx)
+    const float nx = fmaf(-rc.m4pi2U0_dt, mx, r.lx), nv = fmaf(k.dt, mv, r.lv),
+                ne = fmaf(k.dt, me, r.le);
+    float px, pv, pe, ty;
+    jac_t(k, rc, B.c[t], B.s[t], B.v[t], B.e[t], ev, nx, nv, ne, px, pv, pe, ty);
+    add_terms(r, B.ct[t], vt, et, evt, r.lv, r.le, tp);  // times dt/2 at the end
+    add_terms(r, B.c[t], B.v[t], B.e[t], ev, nv, ne, ty);
+    r.A[2] = fmaf(fmaf(h, mv, r.lv), z, r.A[2]);
+    r.lx = fmaf(-rc.m4pi2U0_h, mx + px, r.lx);
     r.lv = fmaf(h, mv + pv, r.lv);
     r.le = fmaf(h, me + pe, r.le);
 }
 
-template <int SCHEME, int VFORM, bool CHECK, class ST>
+// The step's sigma*xi comes from the stage, or (Heun with ZLDS) from the lane's LDS copy zr[64 t]
+// of the window's noise, which then takes no registers in the stage; that lets the Heun
+// predictor's v and e be staged (with 8-step windows they always are). The Euler-Maruyama kernel
+// keeps its noise staged: it has the registers, and an LDS read in its short reverse step costs
+// more than it saves.
+template <int SCHEME, int VFORM, bool CHECK, bool ZLDS, class ST>
 __device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const ST &B, int t,
-                                         int64_t n, const RevCtx &cx, float add_w, Rev &r)
+                                         const float *zr, int64_t n, const RevCtx &cx,
+                                         float add_w, Rev &r)
 {
+    const float z = (ZLDS && SCHEME == 1) ? zr[64 * t] : B.z[t];
     if constexpr (SCHEME == 0)
-        rev_slot_em<VFORM, CHECK>(k, rc, B, t, n, cx, add_w, r);
+        rev_slot_em<VFORM, CHECK>(k, rc, B, t, z, n, cx, add_w, r);
     else
-        rev_slot_heun<CHECK>(k, rc, B, t, n, cx, r);
+        rev_slot_heun<CHECK, ZLDS || ST::B == 8>(k, rc, B, t, z, n, cx, r);
 }
 
 // Reverse the first `hi` slots of a staged sub-window starting at absolute step base, last first.
-template <int SCHEME, int VFORM, bool CHECK, class ST>
+template <int SCHEME, int VFORM, bool CHECK, bool ZLDS, class ST>
 __device__ __forceinline__ void rev_window(const Coef &k, const RevCoef &rc, const ST &B,
-                                           int64_t base, int hi, const RevCtx &cx, float add_w,
-                                           Rev &r)
+                                           const float *zr, int64_t base, int hi,
+                                           const RevCtx &cx, float add_w, Rev &r)
 {
 #pragma unroll
     for (int t = ST::B - 1; t >= 0; --t)
         if (t < hi)
-            rev_slot<SCHEME, VFORM, CHECK>(k, rc, B, t, base + t, cx, add_w, r);
+            rev_slot<SCHEME, VFORM, CHECK, ZLDS>(k, rc, B, t, zr, base + t, cx, add_w, r);
 }
 
 // Recompute the first `hi` slots of the sub-window starting at absolute step base from q,
 // staging them into B.
 template <int SCHEME, bool FROM_LDS, class ST>
 __device__ __forceinline__ void rec_window(const Coef &k, const Stream &s, uint32_t pid,
-                                           Particle &q, int64_t base, int hi, ST &B,
-                                           const float *zl)
+                                           Particle &q, int64_t base, int hi, ST &B, float *zl)
 {
     Noise4 z;
     float xb = q.xf + k.phi;
@@ -441,15 +470,17 @@ __device__ __forceinline__ void rec_window(const Coef &k, const Stream &s, uint3
 
 // One pipeline trip: reverse window m from R while recomputing window m-1 (from q) into W. The
 // sub-window holding the loss-window start (m == m_chk) runs the two halves one after the other.
-template <int SCHEME, int VFORM, bool FROM_LDS, class ST>
+// ZLDS: both windows' noise is in the lane's LDS copy (zr: window m, zl: window m-1).
+template <int SCHEME, int VFORM, bool ZLDS, class ST>
 __device__ __forceinline__ void trip(const Coef &k, const RevCoef &rc, const Stream &s,
                                      uint32_t pid, Particle &q, int64_t m, int64_t m_chk,
-                                     const RevCtx &cx, const ST &R, ST &W, const float *zl, Rev &r)
+                                     const RevCtx &cx, const ST &R, ST &W, const float *zr,
+                                     float *zl, Rev &r)
 {
     constexpr int kB = ST::B;
     if (m == m_chk) {
-        rev_window<SCHEME, VFORM, true>(k, rc, R, m * kB, kB, cx, 0.0f, r);
-        rec_window<SCHEME, FROM_LDS>(k, s, pid, q, (m - 1) * kB, kB, W, zl);
+        rev_window<SCHEME, VFORM, true, ZLDS>(k, rc, R, zr, m * kB, kB, cx, 0.0f, r);
+        rec_window<SCHEME, ZLDS>(k, s, pid, q, (m - 1) * kB, kB, W, zl);
         return;
     }
     const float add_w = (VFORM && m * kB >= cx.wb) ? cx.invW : 0.0f;
@@ -457,23 +488,24 @@ __device__ __forceinline__ void trip(const Coef &k, const RevCoef &rc, const Str
     float xb = q.xf + k.phi;
 #pragma unroll
     for (int t = 0; t < kB; ++t) {
-        rec_slot<SCHEME, FROM_LDS>(k, s, pid, q, xb, z, (m - 1) * kB, t, W, zl);
+        rec_slot<SCHEME, ZLDS>(k, s, pid, q, xb, z, (m - 1) * kB, t, W, zl);
         const int u = kB - 1 - t;
-        rev_slot<SCHEME, VFORM, false>(k, rc, R, u, m * kB + u, cx, add_w, r);
+        rev_slot<SCHEME, VFORM, false, ZLDS>(k, rc, R, u, zr, m * kB + u, cx, add_w, r);
     }
 }
 
 // Reverse a whole staged window with no recomputation beside it.
-template <int SCHEME, int VFORM, class ST>
+template <int SCHEME, int VFORM, bool ZLDS, class ST>
 __device__ __forceinline__ void last_window(const Coef &k, const RevCoef &rc, int64_t m,
-                                            int64_t m_chk, const RevCtx &cx, const ST &R, Rev &r)
+                                            int64_t m_chk, const RevCtx &cx, const ST &R,
+                                            const float *zr, Rev &r)
 {
     constexpr int kB = ST::B;
     if (m == m_chk) {
-        rev_window<SCHEME, VFORM, true>(k, rc, R, m * kB, kB, cx, 0.0f, r);
+        rev_window<SCHEME, VFORM, true, ZLDS>(k, rc, R, zr, m * kB, kB, cx, 0.0f, r);
     } else {
         const float add_w = (VFORM && m * kB >= cx.wb) ? cx.invW : 0.0f;
-        rev_window<SCHEME, VFORM, false>(k, rc, R, m * kB, kB, cx, add_w, r);
+        rev_window<SCHEME, VFORM, false, ZLDS>(k, rc, R, zr, m * kB, kB, cx, add_w, r);
     }
 }
 
@@ -494,7 +526,7 @@ __device__ __forceinline__ void flush(Rev &r, double (&A64)[kSums])
 // instruction stream, so the two dependency chains fill each other's latency (the adjoint runs
 // at one wavefront per SIMD for 2^16-particle ensembles).
 template <int SCHEME, int VFORM, bool ZLDS, int NB>
-__global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
+__global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *__restrict__ rows)
 {
     using ST = Stage<SCHEME, NB>;
     constexpr int kStage = NB;
@@ -502,7 +534,16 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
     Lane L;
     if (*a.status != ABP_OK || !locate(a, L))
         return;
-    const AdjRow &row = a.rows[L.set];
+    // The set's row: through the restrict-qualified table (scalar loads where the constants are
+    // used; the checkpoint stores cannot alias it), or, for the 8-step Euler-Maruyama kernel, which
+    // has registers to spare, copied into registers once.
+    AdjRow row_copy;
+    const AdjRow *rp = rows + L.set;
+    if constexpr (SCHEME == 0 && NB == 8) {
+        row_copy = *rp;
+        rp = &row_copy;
+    }
+    const AdjRow &row = *rp;
     const Coef &k = row.k;
     const RevCoef &rc = row.r;
     const Stream s{a.k0, a.k1, (uint32_t)L.set};
@@ -541,14 +582,19 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
         // each earlier sub-window start; the last one's start state stays in registers
         Particle p[1] = {ck};
         int64_t step = s0;
-        float *zl = nullptr;  // the lane's LDS noise copy of sub-window m0 (ZLDS)
+        // ZLDS: the lane's LDS copy of the segment's noise, 64 floats apart per step from the start
+        // of sub-window m0; zw(m) is sub-window m's part
+        float *zl = nullptr;
         if constexpr (ZLDS)
             zl = zbuf + (size_t)(threadIdx.x >> 6) * a.z_slots * 64 + L.lane;
+        auto zw = [&](int64_t mm) { return ZLDS ? zl + (size_t)(mm - m0) * kStage * 64 : nullptr; };
+        // the segment's last sub-window keeps the noise its staged recomputation draws only where
+        // the reverse sweep reads it back (Heun)
+        float *zlast = (ZLDS && SCHEME == 1) ? zw(m1) : nullptr;
         for (int64_t m = m0; m < m1; ++m) {
             put_state(sub + (size_t)(m - m0) * 7 * N, N, L.g, p[0]);
             if constexpr (ZLDS)
-                level1_window<SCHEME, NB>(k, s, pid[0], p[0], m * kStage,
-                                          zl + (size_t)(m - m0) * kStage * 64);
+                level1_window<SCHEME, NB>(k, s, pid[0], p[0], m * kStage, zw(m));
             else
                 advance<SCHEME, 1, 1>(k, s, pid, p, step, (m + 1) * kStage);
         }
@@ -561,43 +607,48 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a)
         const int hi1 = (int)(s1 - m1 * kStage);
         if (hi1 < kStage) {
             // the run's final sub-window is shorter: recompute and reverse it on its own
-            rec_window<SCHEME, false>(k, s, pid[0], q, m1 * kStage, hi1, SA, nullptr);
-            rev_window<SCHEME, VFORM, true>(k, rc, SA, m1 * kStage, hi1, cx, 0.0f, r);
+            rec_window<SCHEME, false>(k, s, pid[0], q, m1 * kStage, hi1, SA, zlast);
+            rev_window<SCHEME, VFORM, true, ZLDS>(k, rc, SA, zw(m1), m1 * kStage, hi1, cx, 0.0f,
+                                                 r);
             flush(r, A64);
             if (m1 == m0)
                 continue;
             m = m1 - 1;
             q = get_state(sub + (size_t)(m - m0) * 7 * N, N, L.g);
         }
-        // prologue: stage window m into SA
-        rec_window<SCHEME, false>(k, s, pid[0], q, m * kStage, kStage, SA, nullptr);
+        // prologue: stage window m into SA (the segment's last sub-window draws its noise here,
+        // an earlier one has it in LDS already)
+        if (ZLDS && m < m1)
+            rec_window<SCHEME, true>(k, s, pid[0], q, m * kStage, kStage, SA, zw(m));
+        else
+            rec_window<SCHEME, false>(k, s, pid[0], q, m * kStage, kStage, SA, zlast);
         Particle nxt;
         if (m > m0)
             nxt = get_state(sub + (size_t)(m - 1 - m0) * 7 * N, N, L.g);
         // steady state, two windows per trip with the staging buffers swapping roles
         for (;;) {
             if (m == m0) {
-                last_window<SCHEME, VFORM>(k, rc, m, m_chk, cx, SA, r);
+                last_window<SCHEME, VFORM, ZLDS>(k, rc, m, m_chk, cx, SA, zw(m), r);
                 flush(r, A64);
                 break;
             }
             q = nxt;
             if (m - 1 > m0)
                 nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
-            trip<SCHEME, VFORM, ZLDS>(k, rc, s, pid[0], q, m, m_chk, cx, SA, SB,
-                                      zl + (size_t)(m - 1 - m0) * kStage * 64, r);
+            trip<SCHEME, VFORM, ZLDS>(k, rc, s, pid[0], q, m, m_chk, cx, SA, SB, zw(m),
+                                      zw(m - 1), r);
             flush(r, A64);
             --m;
             if (m == m0) {
-                last_window<SCHEME, VFORM>(k, rc, m, m_chk, cx, SB, r);
+                last_window<SCHEME, VFORM, ZLDS>(k, rc, m, m_chk, cx, SB, zw(m), r);
                 flush(r, A64);
                 break;
             }
             q = nxt;
             if (m - 1 > m0)
                 nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
-            trip<SCHEME, VFORM, ZLDS>(k, rc, s, pid[0], q, m, m_chk, cx, SB, SA,
-                                      zl + (size_t)(m - 1 - m0) * kStage * 64, r);
+            trip<SCHEME, VFORM, ZLDS>(k, rc, s, pid[0], q, m, m_chk, cx, SB, SA, zw(m),
+                                      zw(m - 1), r);
             flush(r, A64);
             --m;
         }
@@ -746,7 +797,7 @@ __device__ __forceinline__ AdjRow make_adj_row(const abp_params &p, double dt)
     r.r.four_pi_U0 = (float)(4.0 * kPi * p.U0);
     r.r.a2 = (float)(2.0 * p.a);
     r.r.eight_a = (float)(8.0 * p.a);
-    r.r.m4pi2U0 = (float)(-4.0 * kPi * kPi * p.U0);
+    r.r.m4pi2U0_h = (float)(-4.0 * kPi * kPi * p.U0 * (0.5 * dt));
     r.r.inv2D = (float)(1.0 / (2.0 * p.D));
     r.r.m4pi2U0_dt = (float)(-4.0 * kPi * kPi * p.U0 * dt);
     r.r.d2_dt = (float)(p.d2 * dt);
@@ -761,7 +812,7 @@ __device__ __forceinline__ AdjRow make_adj_row(const abp_params &p, double dt)
 __device__ __forceinline__ bool adj_row_ok(const AdjRow &r)
 {
     const RevCoef &c = r.r;
-    const float f[] = {c.two_pi, c.four_pi_U0, c.a2, c.eight_a, c.m4pi2U0, c.inv2D,
+    const float f[] = {c.two_pi, c.four_pi_U0, c.a2, c.eight_a, c.m4pi2U0_h, c.inv2D,
                        c.m4pi2U0_dt, c.d2_dt, c.g0_dt, c.c_dt, c.m2d2_dt};
     for (float x : f)
         if (!std::isfinite(x))
@@ -859,13 +910,13 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         const int cus = device_cus();
         const bool ahead = cus > 0 && waves <= (int64_t)cus * 4 * 2;
         if (heun && ahead)
-            hipLaunchKernelGGL((k_adj_forward<1, kAhead>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_adj_forward<1, kAhead>), dim3(grid), dim3(256), 0, st, a, a.rows);
         else if (heun)
-            hipLaunchKernelGGL((k_adj_forward<1, 1>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_adj_forward<1, 1>), dim3(grid), dim3(256), 0, st, a, a.rows);
         else if (ahead)
-            hipLaunchKernelGGL((k_adj_forward<0, kAhead>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_adj_forward<0, kAhead>), dim3(grid), dim3(256), 0, st, a, a.rows);
         else
-            hipLaunchKernelGGL((k_adj_forward<0, 1>), dim3(grid), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_adj_forward<0, 1>), dim3(grid), dim3(256), 0, st, a, a.rows);
     } else {
         // B = 16 is the default for both schemes: one wavefront per SIMD. B = 8 (on request) fits
         // two Euler-Maruyama wavefronts per SIMD; the Heun backward runs one wavefront per SIMD at
@@ -874,7 +925,7 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         const int blocks_per_cu = (!heun && B == 8) ? 2 : 1;
         // level-1 noise in LDS when every resident block's copy fits (and one block's share is
         // allowed); else it is regenerated
-        a.z_slots = (int32_t)(a.K - B);
+        a.z_slots = (int32_t)(heun ? a.K : a.K - B);
         const size_t z_bytes = sizeof(float) * 64 * (size_t)a.z_slots * 4;  // per 256-thread block
         const bool zlds = a.z_slots > 0 && z_bytes * blocks_per_cu <= lds_per_cu_limit() &&
                           z_bytes <= lds_per_block_limit();
@@ -882,32 +933,32 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         const dim3 g3(grid), b3(256);
         if (heun && B == 16) {
             if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 16>), g3, b3, lds, st, a);
+                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 16>), g3, b3, lds, st, a, a.rows);
             else
-                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 16>), g3, b3, 0, st, a);
+                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 16>), g3, b3, 0, st, a, a.rows);
         } else if (heun) {
             if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 8>), g3, b3, lds, st, a);
+                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 8>), g3, b3, lds, st, a, a.rows);
             else
-                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 8>), g3, b3, 0, st, a);
+                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 8>), g3, b3, 0, st, a, a.rows);
         } else if (B == 8) {
             if (a.vform && zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 8>), g3, b3, lds, st, a);
+                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 8>), g3, b3, lds, st, a, a.rows);
             else if (a.vform)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 8>), g3, b3, 0, st, a);
+                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 8>), g3, b3, 0, st, a, a.rows);
             else if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 8>), g3, b3, lds, st, a);
+                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 8>), g3, b3, lds, st, a, a.rows);
             else
-                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 8>), g3, b3, 0, st, a);
+                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 8>), g3, b3, 0, st, a, a.rows);
         } else {
             if (a.vform && zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 16>), g3, b3, lds, st, a);
+                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 16>), g3, b3, lds, st, a, a.rows);
             else if (a.vform)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 16>), g3, b3, 0, st, a);
+                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 16>), g3, b3, 0, st, a, a.rows);
             else if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 16>), g3, b3, lds, st, a);
+                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 16>), g3, b3, lds, st, a, a.rows);
             else
-                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 16>), g3, b3, 0, st, a);
+                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 16>), g3, b3, 0, st, a, a.rows);
         }
     }
     if (hipGetLastError() != hipSuccess)
