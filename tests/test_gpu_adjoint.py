@@ -40,13 +40,17 @@ def _params(theta_row):
     return p
 
 
-def test_loss_equals_forward_mean_and_gradient_is_checkpoint_invariant(gpu):
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_loss_equals_forward_mean_and_gradient_is_checkpoint_invariant(gpu, scheme):
+    """Bit-identical gradients for every K. For Heun, K = 1203 (rounded to 1216) leaves the
+    segment's noise out of LDS, so the reverse sweep recomputes the predictor's v and e instead of
+    reading them from the stage: the two forms must agree bit for bit."""
     from paper_1104_2499_amd import adjoint, api
 
     theta = _theta(3, jitter=0.2, seed=1)
     grads = []
     for K in (100, 37, 1203, 8):
-        cfg = adjoint.AdjointConfig(n=300, steps=1203, window=401, ckpt=K, seed=5)
+        cfg = adjoint.AdjointConfig(n=300, steps=1203, window=401, ckpt=K, seed=5, scheme=scheme)
         rows = adjoint.param_rows(theta, cfg)
         ws = adjoint.workspace(3, cfg)
         loss = adjoint.forward(rows, cfg, ws)
@@ -54,7 +58,7 @@ def test_loss_equals_forward_mean_and_gradient_is_checkpoint_invariant(gpu):
                                  per_particle=True)
         grads.append((g.cpu().numpy(), gp.cpu().numpy()))
         for k in range(3):
-            r = api.run(_params(theta[k]), n=300, steps=1203, window=401, scheme="em", seed=5,
+            r = api.run(_params(theta[k]), n=300, steps=1203, window=401, scheme=scheme, seed=5,
                         bins=0, set_id=k)
             assert float(loss[k].cpu()) == r.mean_v
     for g, gp in grads[1:]:
