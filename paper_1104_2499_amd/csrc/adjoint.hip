@@ -14,14 +14,14 @@
 // multiple of 16). Then, for each sub-window in reverse, it restores the sub-checkpoint,
 // recomputes the sub-window while staging the values the reverse step needs (cos and sin of the
 // phase, v, e at every point where the drift is evaluated, and sigma*xi) in registers, and runs
-// the adjoint recursion backwards over it. When the segment's noise fits in LDS (K steps x 64
-// lanes x 4 bytes per wavefront; one four-wavefront block per CU with 16-step staging, two with
-// 8-step staging), level 1 keeps each sigma*xi it draws there and the staged recomputation reads
-// it back instead of running Philox and Box-Muller a second time. For Heun the last sub-window's
-// noise (drawn by its staged recomputation) is kept too, K steps in all, and the reverse steps
-// read it there instead of from registers; Euler-Maruyama keeps K - B steps. The recomputation reproduces
-// the forward bits exactly (the integrator's state is resumable mid-span), so the result does
-// not depend on K. Per-step gradient terms are summed in FP32 within each absolute B-step window
+// the adjoint recursion backwards over it. When the segment's noise fits in LDS (at most K steps
+// x 64 lanes x 4 bytes per wavefront; one four-wavefront block per CU with 16-step staging, two
+// with 8-step staging), level 1 keeps each sigma*xi it draws there and the staged recomputation
+// reads it back instead of running Philox and Box-Muller a second time. Euler-Maruyama keeps the
+// K - B steps level 1 draws; Heun keeps the last sub-window's noise too (drawn by its staged
+// recomputation), K steps in all, and its reverse steps read sigma*xi there instead of from
+// registers. The recomputation reproduces the forward bits exactly (the integrator's state is
+// resumable mid-span), so the result does not depend on K. Per-step gradient terms are summed in FP32 within each absolute B-step window
 // and in FP64 across windows (that grouping does not depend on K either); tiles of 64 particles
 // and sets are then reduced in a fixed order.
 //
