@@ -21,9 +21,9 @@
 // K - B steps level 1 draws; Heun keeps the last sub-window's noise too (drawn by its staged
 // recomputation), K steps in all, and its reverse steps read sigma*xi there instead of from
 // registers. The recomputation reproduces the forward bits exactly (the integrator's state is
-// resumable mid-span), so the result does not depend on K. Per-step gradient terms are summed in FP32 within each absolute B-step window
-// and in FP64 across windows (that grouping does not depend on K either); tiles of 64 particles
-// and sets are then reduced in a fixed order.
+// resumable mid-span), so the result does not depend on K. Per-step gradient terms are summed in
+// FP32 within each absolute B-step window and in FP64 across windows (that grouping does not
+// depend on K either); tiles of 64 particles and sets are then reduced in a fixed order.
 //
 // The parameter table is a device array: each call first computes and checks every set's
 // constants on the device (k_adj_rows), raising a status word in the workspace for a set that
