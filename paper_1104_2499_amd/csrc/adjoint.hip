@@ -233,13 +233,13 @@ struct Stage<1, NB> {
     float c[B], s[B], v[B], e[B], ct[B], st[B], vt[B], et[B], z[B];
 };
 
-// Recompute slot t of a sub-window (absolute step base + t), staging its inputs. The noise is
-// regenerated or (FROM_LDS) read from the lane's LDS copy zl[64 t] kept by level 1; regenerated
-// noise is also kept there when zl is given. The staged predictor repeats step_heun's own
-// expressions (the compiler merges the two), so it holds the values that step saw.
+// Recompute slot t of a sub-window (absolute step base + t), staging its inputs in the stage's
+// slot ps. The noise is regenerated or (FROM_LDS) read from the lane's LDS copy zl[64 t] kept by
+// level 1; regenerated noise is also kept there when zl is given. The staged predictor repeats
+// step_heun's own expressions (the compiler merges the two), so it holds the values that step saw.
 template <int SCHEME, bool FROM_LDS, class ST>
 __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_t pid, Particle &q,
-                                         float &xb, Noise4 &z, int64_t base, int t, ST &B,
+                                         float &xb, Noise4 &z, int64_t base, int t, int ps, ST &B,
                                          float *zl)
 {
     float zs;
@@ -253,18 +253,18 @@ __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_
             zl[64 * t] = zs;
     }
     const float xc = xb + q.lx, vc = q.v + q.lv, ec = q.e + q.le;
-    B.c[t] = __builtin_amdgcn_cosf(xc);
-    B.s[t] = __builtin_amdgcn_sinf(xc);
-    B.v[t] = vc;
-    B.e[t] = ec;
-    B.z[t] = zs;
+    B.c[ps] = __builtin_amdgcn_cosf(xc);
+    B.s[ps] = __builtin_amdgcn_sinf(xc);
+    B.v[ps] = vc;
+    B.e[ps] = ec;
+    B.z[ps] = zs;
     if constexpr (SCHEME == 1) {
         const float xp = fmaf(vc, k.dt, xc);
-        B.ct[t] = __builtin_amdgcn_cosf(xp);
-        B.st[t] = __builtin_amdgcn_sinf(xp);
+        B.ct[ps] = __builtin_amdgcn_cosf(xp);
+        B.st[ps] = __builtin_amdgcn_sinf(xp);
         float fv0, fe0;
         drift(k, xc, vc, ec, fv0, fe0);
-        heun_predictor_ve(k, vc, ec, fv0, fe0, zs, B.vt[t], B.et[t]);
+        heun_predictor_ve(k, vc, ec, fv0, fe0, zs, B.vt[ps], B.et[ps]);
     }
     step<SCHEME>(k, q, xb, zs);
     if ((t & (kSpan - 1)) == kSpan - 1) {
@@ -430,20 +430,31 @@ __device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc,
 // predictor's v and e be staged (with 8-step windows they always are). The Euler-Maruyama kernel
 // keeps its noise staged: it has the registers, and an LDS read in its short reverse step costs
 // more than it saves.
+// Slot t of a window (step base + t) is staged in slot ps of the stage (see slot_of).
 template <int SCHEME, int VFORM, bool CHECK, bool ZLDS, class ST>
 __device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const ST &B, int t,
-                                         const float *zr, int64_t n, const RevCtx &cx,
+                                         int ps, const float *zr, int64_t n, const RevCtx &cx,
                                          float add_w, Rev &r)
 {
-    const float z = (ZLDS && SCHEME == 1) ? zr[64 * t] : B.z[t];
+    const float z = (ZLDS && SCHEME == 1) ? zr[64 * t] : B.z[ps];
     if constexpr (SCHEME == 0)
-        rev_slot_em<VFORM, CHECK>(k, rc, B, t, z, n, cx, add_w, r);
+        rev_slot_em<VFORM, CHECK>(k, rc, B, ps, z, n, cx, add_w, r);
     else
-        rev_slot_heun<CHECK, ZLDS || ST::B == 8>(k, rc, B, t, z, n, cx, r);
+        rev_slot_heun<CHECK, ZLDS || ST::B == 8>(k, rc, B, ps, z, n, cx, r);
+}
+
+// One stage buffer serves the whole pipeline. A window is staged in order (slot t in stage slot
+// t) or reversed (slot t in stage slot NB-1-t); while a trip reverses a window it recomputes the
+// next one into the stage slots the reverse steps have just read, so the layout flips with every
+// trip and the stage holds one window, not two.
+template <bool REVERSED, int NB>
+__device__ __forceinline__ constexpr int slot_of(int t)
+{
+    return REVERSED ? NB - 1 - t : t;
 }
 
 // Reverse the first `hi` slots of a staged sub-window starting at absolute step base, last first.
-template <int SCHEME, int VFORM, bool CHECK, bool ZLDS, class ST>
+template <int SCHEME, int VFORM, bool CHECK, bool ZLDS, bool REVERSED, class ST>
 __device__ __forceinline__ void rev_window(const Coef &k, const RevCoef &rc, const ST &B,
                                            const float *zr, int64_t base, int hi,
                                            const RevCtx &cx, float add_w, Rev &r)
@@ -451,12 +462,13 @@ __device__ __forceinline__ void rev_window(const Coef &k, const RevCoef &rc, con
 #pragma unroll
     for (int t = ST::B - 1; t >= 0; --t)
         if (t < hi)
-            rev_slot<SCHEME, VFORM, CHECK, ZLDS>(k, rc, B, t, zr, base + t, cx, add_w, r);
+            rev_slot<SCHEME, VFORM, CHECK, ZLDS>(k, rc, B, t, slot_of<REVERSED, ST::B>(t), zr,
+                                                 base + t, cx, add_w, r);
 }
 
 // Recompute the first `hi` slots of the sub-window starting at absolute step base from q,
 // staging them into B.
-template <int SCHEME, bool FROM_LDS, class ST>
+template <int SCHEME, bool FROM_LDS, bool REVERSED, class ST>
 __device__ __forceinline__ void rec_window(const Coef &k, const Stream &s, uint32_t pid,
                                            Particle &q, int64_t base, int hi, ST &B, float *zl)
 {
@@ -465,22 +477,23 @@ __device__ __forceinline__ void rec_window(const Coef &k, const Stream &s, uint3
 #pragma unroll
     for (int t = 0; t < ST::B; ++t)
         if (t < hi)
-            rec_slot<SCHEME, FROM_LDS>(k, s, pid, q, xb, z, base, t, B, zl);
+            rec_slot<SCHEME, FROM_LDS>(k, s, pid, q, xb, z, base, t,
+                                       slot_of<REVERSED, ST::B>(t), B, zl);
 }
 
-// One pipeline trip: reverse window m from R while recomputing window m-1 (from q) into W. The
+// One pipeline trip: reverse window m, staged with layout REVERSED, while recomputing window m-1
+// (from q) into the stage slots just read (so window m-1 comes out with the other layout). The
 // sub-window holding the loss-window start (m == m_chk) runs the two halves one after the other.
 // ZLDS: both windows' noise is in the lane's LDS copy (zr: window m, zl: window m-1).
-template <int SCHEME, int VFORM, bool ZLDS, class ST>
+template <int SCHEME, int VFORM, bool ZLDS, bool REVERSED, class ST>
 __device__ __forceinline__ void trip(const Coef &k, const RevCoef &rc, const Stream &s,
                                      uint32_t pid, Particle &q, int64_t m, int64_t m_chk,
-                                     const RevCtx &cx, const ST &R, ST &W, const float *zr,
-                                     float *zl, Rev &r)
+                                     const RevCtx &cx, ST &S, const float *zr, float *zl, Rev &r)
 {
     constexpr int kB = ST::B;
     if (m == m_chk) {
-        rev_window<SCHEME, VFORM, true, ZLDS>(k, rc, R, zr, m * kB, kB, cx, 0.0f, r);
-        rec_window<SCHEME, ZLDS>(k, s, pid, q, (m - 1) * kB, kB, W, zl);
+        rev_window<SCHEME, VFORM, true, ZLDS, REVERSED>(k, rc, S, zr, m * kB, kB, cx, 0.0f, r);
+        rec_window<SCHEME, ZLDS, !REVERSED>(k, s, pid, q, (m - 1) * kB, kB, S, zl);
         return;
     }
     const float add_w = (VFORM && m * kB >= cx.wb) ? cx.invW : 0.0f;
@@ -488,24 +501,26 @@ __device__ __forceinline__ void trip(const Coef &k, const RevCoef &rc, const Str
     float xb = q.xf + k.phi;
 #pragma unroll
     for (int t = 0; t < kB; ++t) {
-        rec_slot<SCHEME, ZLDS>(k, s, pid, q, xb, z, (m - 1) * kB, t, W, zl);
+        // window m's slot u and window m-1's slot t share stage slot ps
         const int u = kB - 1 - t;
-        rev_slot<SCHEME, VFORM, false, ZLDS>(k, rc, R, u, zr, m * kB + u, cx, add_w, r);
+        const int ps = slot_of<REVERSED, kB>(u);
+        rev_slot<SCHEME, VFORM, false, ZLDS>(k, rc, S, u, ps, zr, m * kB + u, cx, add_w, r);
+        rec_slot<SCHEME, ZLDS>(k, s, pid, q, xb, z, (m - 1) * kB, t, ps, S, zl);
     }
 }
 
 // Reverse a whole staged window with no recomputation beside it.
-template <int SCHEME, int VFORM, bool ZLDS, class ST>
+template <int SCHEME, int VFORM, bool ZLDS, bool REVERSED, class ST>
 __device__ __forceinline__ void last_window(const Coef &k, const RevCoef &rc, int64_t m,
-                                            int64_t m_chk, const RevCtx &cx, const ST &R,
+                                            int64_t m_chk, const RevCtx &cx, const ST &S,
                                             const float *zr, Rev &r)
 {
     constexpr int kB = ST::B;
     if (m == m_chk) {
-        rev_window<SCHEME, VFORM, true, ZLDS>(k, rc, R, zr, m * kB, kB, cx, 0.0f, r);
+        rev_window<SCHEME, VFORM, true, ZLDS, REVERSED>(k, rc, S, zr, m * kB, kB, cx, 0.0f, r);
     } else {
         const float add_w = (VFORM && m * kB >= cx.wb) ? cx.invW : 0.0f;
-        rev_window<SCHEME, VFORM, false, ZLDS>(k, rc, R, zr, m * kB, kB, cx, add_w, r);
+        rev_window<SCHEME, VFORM, false, ZLDS, REVERSED>(k, rc, S, zr, m * kB, kB, cx, add_w, r);
     }
 }
 
@@ -522,9 +537,9 @@ __device__ __forceinline__ void flush(Rev &r, double (&A64)[kSums])
 // estimator (see abp_adjoint_cfg.lookback; Euler-Maruyama only).
 //
 // Within a segment the sub-windows are processed as a software pipeline: while window m is
-// reversed from one staging buffer, window m-1 is recomputed into the other, in the same
-// instruction stream, so the two dependency chains fill each other's latency (the adjoint runs
-// at one wavefront per SIMD for 2^16-particle ensembles).
+// reversed from the stage, window m-1 is recomputed into the stage slots already read, in the
+// same instruction stream, so the two dependency chains fill each other's latency (the adjoint
+// runs at one wavefront per SIMD for 2^16-particle ensembles).
 template <int SCHEME, int VFORM, bool ZLDS, int NB>
 __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *__restrict__ rows)
 {
@@ -601,54 +616,54 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *_
         if (j > 0)
             ck = get_state(a.ckpt + (size_t)(j - 1) * 7 * N, N, L.g);
 
-        ST SA, SB;
+        ST S;  // the stage (one window; see slot_of)
         Particle q = p[0];
         int64_t m = m1;
         const int hi1 = (int)(s1 - m1 * kStage);
         if (hi1 < kStage) {
             // the run's final sub-window is shorter: recompute and reverse it on its own
-            rec_window<SCHEME, false>(k, s, pid[0], q, m1 * kStage, hi1, SA, zlast);
-            rev_window<SCHEME, VFORM, true, ZLDS>(k, rc, SA, zw(m1), m1 * kStage, hi1, cx, 0.0f,
-                                                 r);
+            rec_window<SCHEME, false, false>(k, s, pid[0], q, m1 * kStage, hi1, S, zlast);
+            rev_window<SCHEME, VFORM, true, ZLDS, false>(k, rc, S, zw(m1), m1 * kStage, hi1, cx,
+                                                        0.0f, r);
             flush(r, A64);
             if (m1 == m0)
                 continue;
             m = m1 - 1;
             q = get_state(sub + (size_t)(m - m0) * 7 * N, N, L.g);
         }
-        // prologue: stage window m into SA (the segment's last sub-window draws its noise here,
+        // prologue: stage window m in order (the segment's last sub-window draws its noise here,
         // an earlier one has it in LDS already)
         if (ZLDS && m < m1)
-            rec_window<SCHEME, true>(k, s, pid[0], q, m * kStage, kStage, SA, zw(m));
+            rec_window<SCHEME, true, false>(k, s, pid[0], q, m * kStage, kStage, S, zw(m));
         else
-            rec_window<SCHEME, false>(k, s, pid[0], q, m * kStage, kStage, SA, zlast);
+            rec_window<SCHEME, false, false>(k, s, pid[0], q, m * kStage, kStage, S, zlast);
         Particle nxt;
         if (m > m0)
             nxt = get_state(sub + (size_t)(m - 1 - m0) * 7 * N, N, L.g);
-        // steady state, two windows per trip with the staging buffers swapping roles
+        // steady state, two trips per loop pass: the stage's layout is in order at the top
         for (;;) {
             if (m == m0) {
-                last_window<SCHEME, VFORM, ZLDS>(k, rc, m, m_chk, cx, SA, zw(m), r);
+                last_window<SCHEME, VFORM, ZLDS, false>(k, rc, m, m_chk, cx, S, zw(m), r);
                 flush(r, A64);
                 break;
             }
             q = nxt;
             if (m - 1 > m0)
                 nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
-            trip<SCHEME, VFORM, ZLDS>(k, rc, s, pid[0], q, m, m_chk, cx, SA, SB, zw(m),
-                                      zw(m - 1), r);
+            trip<SCHEME, VFORM, ZLDS, false>(k, rc, s, pid[0], q, m, m_chk, cx, S, zw(m),
+                                             zw(m - 1), r);
             flush(r, A64);
             --m;
             if (m == m0) {
-                last_window<SCHEME, VFORM, ZLDS>(k, rc, m, m_chk, cx, SB, zw(m), r);
+                last_window<SCHEME, VFORM, ZLDS, true>(k, rc, m, m_chk, cx, S, zw(m), r);
                 flush(r, A64);
                 break;
             }
             q = nxt;
             if (m - 1 > m0)
                 nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
-            trip<SCHEME, VFORM, ZLDS>(k, rc, s, pid[0], q, m, m_chk, cx, SB, SA, zw(m),
-                                      zw(m - 1), r);
+            trip<SCHEME, VFORM, ZLDS, true>(k, rc, s, pid[0], q, m, m_chk, cx, S, zw(m),
+                                            zw(m - 1), r);
             flush(r, A64);
             --m;
         }
