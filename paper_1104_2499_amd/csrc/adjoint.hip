@@ -78,6 +78,7 @@ struct AdjArgs {
     float rho;        // per-step decay of the adjoint (1 = exact gradient)
     int32_t vform;    // 1: the loss enters as (1/W) sum of v_n over the window (used with rho < 1)
     int32_t z_slots;  // steps of noise each lane keeps in LDS (Heun K, Euler-Maruyama K - B)
+    int32_t lds_wave;  // floats of LDS per wavefront (noise, then sub-checkpoints when SUBL)
 };
 
 constexpr int kAlign = 16;    // checkpoint intervals are multiples of this
@@ -240,11 +241,11 @@ struct Stage<1, NB> {
 template <int SCHEME, bool FROM_LDS, class ST>
 __device__ __forceinline__ void rec_slot(const Coef &k, const Stream &s, uint32_t pid, Particle &q,
                                          float &xb, Noise4 &z, int64_t base, int t, int ps, ST &B,
-                                         float *zl)
+                                         float *zl, const float *zpre = nullptr)
 {
     float zs;
     if constexpr (FROM_LDS) {
-        zs = zl[64 * t];
+        zs = zpre ? zpre[t] : zl[64 * t];
     } else {
         if ((t & 3) == 0)
             z = noise_block((uint32_t)((base + t) >> 2), pid, s.set, s.k0, s.k1, k.bm);
@@ -434,9 +435,9 @@ __device__ __forceinline__ void rev_slot_heun(const Coef &k, const RevCoef &rc,
 template <int SCHEME, int VFORM, bool CHECK, bool ZLDS, class ST>
 __device__ __forceinline__ void rev_slot(const Coef &k, const RevCoef &rc, const ST &B, int t,
                                          int ps, const float *zr, int64_t n, const RevCtx &cx,
-                                         float add_w, Rev &r)
+                                         float add_w, Rev &r, const float *zpre = nullptr)
 {
-    const float z = (ZLDS && SCHEME == 1) ? zr[64 * t] : B.z[ps];
+    const float z = (ZLDS && SCHEME == 1) ? (zpre ? zpre[t] : zr[64 * t]) : B.z[ps];
     if constexpr (SCHEME == 0)
         rev_slot_em<VFORM, CHECK>(k, rc, B, ps, z, n, cx, add_w, r);
     else
@@ -499,13 +500,34 @@ __device__ __forceinline__ void trip(const Coef &k, const RevCoef &rc, const Str
     const float add_w = (VFORM && m * kB >= cx.wb) ? cx.invW : 0.0f;
     Noise4 z;
     float xb = q.xf + k.phi;
+    // ZLDS: both windows' noise is read from LDS into registers before the steps, so that no step
+    // waits for an LDS read issued just before it (at one wavefront per SIMD nothing else hides
+    // that latency)
+    float zrec[kB], zrev[kB];
+    if constexpr (ZLDS) {
+#pragma unroll
+        for (int t = 0; t < kB; ++t) {
+            zrec[t] = zl[64 * t];
+            if constexpr (SCHEME == 1)
+                zrev[t] = zr[64 * t];
+        }
+        // the values are used here, before the steps: the reads complete together
+#pragma unroll
+        for (int t = 0; t < kB; ++t) {
+            asm volatile("" ::"v"(zrec[t]));
+            if constexpr (SCHEME == 1)
+                asm volatile("" ::"v"(zrev[t]));
+        }
+    }
 #pragma unroll
     for (int t = 0; t < kB; ++t) {
         // window m's slot u and window m-1's slot t share stage slot ps
         const int u = kB - 1 - t;
         const int ps = slot_of<REVERSED, kB>(u);
-        rev_slot<SCHEME, VFORM, false, ZLDS>(k, rc, S, u, ps, zr, m * kB + u, cx, add_w, r);
-        rec_slot<SCHEME, ZLDS>(k, s, pid, q, xb, z, (m - 1) * kB, t, ps, S, zl);
+        rev_slot<SCHEME, VFORM, false, ZLDS>(k, rc, S, u, ps, zr, m * kB + u, cx, add_w, r,
+                                             ZLDS ? zrev : nullptr);
+        rec_slot<SCHEME, ZLDS>(k, s, pid, q, xb, z, (m - 1) * kB, t, ps, S, zl,
+                               ZLDS ? zrec : nullptr);
     }
 }
 
@@ -540,12 +562,18 @@ __device__ __forceinline__ void flush(Rev &r, double (&A64)[kSums])
 // reversed from the stage, window m-1 is recomputed into the stage slots already read, in the
 // same instruction stream, so the two dependency chains fill each other's latency (the adjoint
 // runs at one wavefront per SIMD for 2^16-particle ensembles).
-template <int SCHEME, int VFORM, bool ZLDS, int NB>
+//
+// SUBL (with ZLDS): the segment's sub-checkpoints are kept in LDS too, after the noise, so that
+// reading the next one costs an LDS read rather than an L2 round trip (the compiler parks the
+// prefetched values in accumulation registers, which waits for them).
+template <int SCHEME, int VFORM, bool ZLDS, int NB, bool SUBL>
 __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *__restrict__ rows)
 {
     using ST = Stage<SCHEME, NB>;
     constexpr int kStage = NB;
-    extern __shared__ float zbuf[];  // ZLDS: [waves per block][z_slots][64]
+    // ZLDS: per wavefront, [z_slots][64] floats of noise; SUBL: then [K/NB - 1][7][64] floats of
+    // sub-checkpoints
+    extern __shared__ float zbuf[];
     Lane L;
     if (*a.status != ABP_OK || !locate(a, L))
         return;
@@ -582,8 +610,17 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *_
     for (int i = 0; i < kSums; ++i)
         r.A[i] = 0.0f;
     double A64[kSums] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    float *sub = a.sub;
     const int64_t N = a.N;
+    // sub-checkpoint planes: in workspace memory (stride N, slot g) or in the wavefront's LDS
+    // (stride 64, slot lane)
+    float *sub = a.sub;
+    int64_t sN = N, sg = L.g;
+    float *const lds_wave = zbuf + (size_t)(threadIdx.x >> 6) * a.lds_wave;
+    if constexpr (SUBL) {
+        sub = lds_wave + (size_t)a.z_slots * 64;
+        sN = 64;
+        sg = L.lane;
+    }
 
     const int64_t n_seg = (a.S + a.K - 1) / a.K;
     // Memory reads are issued one stage ahead of their use (the next segment's checkpoint while
@@ -601,13 +638,13 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *_
         // of sub-window m0; zw(m) is sub-window m's part
         float *zl = nullptr;
         if constexpr (ZLDS)
-            zl = zbuf + (size_t)(threadIdx.x >> 6) * a.z_slots * 64 + L.lane;
+            zl = lds_wave + L.lane;
         auto zw = [&](int64_t mm) { return ZLDS ? zl + (size_t)(mm - m0) * kStage * 64 : nullptr; };
         // the segment's last sub-window keeps the noise its staged recomputation draws only where
         // the reverse sweep reads it back (Heun)
         float *zlast = (ZLDS && SCHEME == 1) ? zw(m1) : nullptr;
         for (int64_t m = m0; m < m1; ++m) {
-            put_state(sub + (size_t)(m - m0) * 7 * N, N, L.g, p[0]);
+            put_state(sub + (size_t)(m - m0) * 7 * sN, sN, sg, p[0]);
             if constexpr (ZLDS)
                 level1_window<SCHEME, NB>(k, s, pid[0], p[0], m * kStage, zw(m));
             else
@@ -629,7 +666,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *_
             if (m1 == m0)
                 continue;
             m = m1 - 1;
-            q = get_state(sub + (size_t)(m - m0) * 7 * N, N, L.g);
+            q = get_state(sub + (size_t)(m - m0) * 7 * sN, sN, sg);
         }
         // prologue: stage window m in order (the segment's last sub-window draws its noise here,
         // an earlier one has it in LDS already)
@@ -639,7 +676,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *_
             rec_window<SCHEME, false, false>(k, s, pid[0], q, m * kStage, kStage, S, zlast);
         Particle nxt;
         if (m > m0)
-            nxt = get_state(sub + (size_t)(m - 1 - m0) * 7 * N, N, L.g);
+            nxt = get_state(sub + (size_t)(m - 1 - m0) * 7 * sN, sN, sg);
         // steady state, two trips per loop pass: the stage's layout is in order at the top
         for (;;) {
             if (m == m0) {
@@ -649,7 +686,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *_
             }
             q = nxt;
             if (m - 1 > m0)
-                nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
+                nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * sN, sN, sg);
             trip<SCHEME, VFORM, ZLDS, false>(k, rc, s, pid[0], q, m, m_chk, cx, S, zw(m),
                                              zw(m - 1), r);
             flush(r, A64);
@@ -661,7 +698,7 @@ __global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *_
             }
             q = nxt;
             if (m - 1 > m0)
-                nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * N, N, L.g);
+                nxt = get_state(sub + (size_t)(m - 2 - m0) * 7 * sN, sN, sg);
             trip<SCHEME, VFORM, ZLDS, true>(k, rc, s, pid[0], q, m, m_chk, cx, S, zw(m),
                                             zw(m - 1), r);
             flush(r, A64);
@@ -941,39 +978,67 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         // level-1 noise in LDS when every resident block's copy fits (and one block's share is
         // allowed); else it is regenerated
         a.z_slots = (int32_t)(heun ? a.K : a.K - B);
-        const size_t z_bytes = sizeof(float) * 64 * (size_t)a.z_slots * 4;  // per 256-thread block
-        const bool zlds = a.z_slots > 0 && z_bytes * blocks_per_cu <= lds_per_cu_limit() &&
-                          z_bytes <= lds_per_block_limit();
-        const size_t lds = zlds ? z_bytes : 0;
+        // per 256-thread block (4 wavefronts): the noise, and with 16-step staging (one block per
+        // CU) the sub-checkpoints of one segment (all but its last sub-window)
+        const auto fits = [&](size_t bytes) {
+            return bytes * blocks_per_cu <= lds_per_cu_limit() && bytes <= lds_per_block_limit();
+        };
+        const size_t z_floats = (size_t)a.z_slots * 64;
+        const size_t sub_floats = (size_t)(a.K / B - 1) * 7 * 64;
+        const bool zlds = a.z_slots > 0 && fits(4 * sizeof(float) * z_floats);
+        const bool subl = zlds && B == 16 && fits(4 * sizeof(float) * (z_floats + sub_floats));
+        a.lds_wave = (int32_t)(z_floats + (subl ? sub_floats : 0));
+        const size_t lds = zlds ? 4 * sizeof(float) * (size_t)a.lds_wave : 0;
         const dim3 g3(grid), b3(256);
         if (heun && B == 16) {
-            if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 16>), g3, b3, lds, st, a, a.rows);
+            if (subl)
+                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 16, true>), g3, b3, lds, st, a,
+                                   a.rows);
+            else if (zlds)
+                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 16, false>), g3, b3, lds, st, a,
+                                   a.rows);
             else
-                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 16>), g3, b3, 0, st, a, a.rows);
+                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 16, false>), g3, b3, 0, st, a,
+                                   a.rows);
         } else if (heun) {
             if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 8>), g3, b3, lds, st, a, a.rows);
+                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 8, false>), g3, b3, lds, st, a,
+                                   a.rows);
             else
-                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 8>), g3, b3, 0, st, a, a.rows);
+                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 8, false>), g3, b3, 0, st, a,
+                                   a.rows);
         } else if (B == 8) {
             if (a.vform && zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 8>), g3, b3, lds, st, a, a.rows);
+                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 8, false>), g3, b3, lds, st, a,
+                                   a.rows);
             else if (a.vform)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 8>), g3, b3, 0, st, a, a.rows);
+                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 8, false>), g3, b3, 0, st, a,
+                                   a.rows);
             else if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 8>), g3, b3, lds, st, a, a.rows);
+                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 8, false>), g3, b3, lds, st, a,
+                                   a.rows);
             else
-                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 8>), g3, b3, 0, st, a, a.rows);
+                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 8, false>), g3, b3, 0, st, a,
+                                   a.rows);
         } else {
-            if (a.vform && zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 16>), g3, b3, lds, st, a, a.rows);
+            if (a.vform && subl)
+                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 16, true>), g3, b3, lds, st, a,
+                                   a.rows);
+            else if (a.vform && zlds)
+                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 16, false>), g3, b3, lds, st, a,
+                                   a.rows);
             else if (a.vform)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 16>), g3, b3, 0, st, a, a.rows);
+                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 16, false>), g3, b3, 0, st, a,
+                                   a.rows);
+            else if (subl)
+                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 16, true>), g3, b3, lds, st, a,
+                                   a.rows);
             else if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 16>), g3, b3, lds, st, a, a.rows);
+                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 16, false>), g3, b3, lds, st, a,
+                                   a.rows);
             else
-                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 16>), g3, b3, 0, st, a, a.rows);
+                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 16, false>), g3, b3, 0, st, a,
+                                   a.rows);
         }
     }
     if (hipGetLastError() != hipSuccess)
