@@ -65,15 +65,18 @@ def mix_ceiling() -> dict:
     return out
 
 
-KERNEL_SOURCES = ("common.hpp", "device.hpp", "reduce.hpp", "forward.hip")
+KERNEL_SOURCES = ("common.hpp", "device.hpp", "reduce.hpp", "integrate.hpp", "integrate_heun.hip")
 
 
 def source_hash() -> str:
-    """Hash of the sources the single-set integrator kernel is built from."""
+    """Hash of the sources the Heun integrator kernel is built from, and of its build flags."""
+    from paper_1104_2499_amd import build
+
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1104_2499_amd", "csrc")
     for name in KERNEL_SOURCES:
         h.update(open(os.path.join(csrc, name), "rb").read())
+    h.update(" ".join(build.flags_for(os.path.join(csrc, KERNEL_SOURCES[-1]))).encode())
     return h.hexdigest()[:16]
 
 
