@@ -467,8 +467,8 @@ def adjoint_batched_bench(stage: int, ckpt: int, reps: int = 3) -> dict:
 
 
 def adjoint_batched_item(iters: int = 50) -> dict:
-    """The batched-adjoint workload (1024 sets x 1024 particles x 5e4 EM steps, W = 1e4; K = 80,
-    8-step staging): one forward + backward iteration against the plain batched forward of the
+    """The batched-adjoint workload (1024 sets x 1024 particles x 5e4 EM steps, W = 1e4; K = 48,
+    16-step staging, two wavefronts per SIMD): one forward + backward iteration against the plain batched forward of the
     same sets, then the 50-iteration Adam loop on (U0, a, d2) with the exact pathwise gradient."""
     import numpy as np
     import torch

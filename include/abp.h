@@ -248,10 +248,11 @@ typedef struct abp_adjoint_cfg {
                             biased, bounded-variance estimator for long chaotic horizons) */
     int32_t scheme;      /* ABP_EM or ABP_HEUN: the map whose discrete adjoint is taken */
     int32_t stage_steps; /* steps the backward pass stages in registers at a time: 0 = default
-                            (16), or 8 or 16. For Euler-Maruyama 8 lets two wavefronts share a
-                            SIMD (faster for ensembles of more than ~2 wavefronts per SIMD); the
-                            Heun backward runs one wavefront per SIMD either way and is faster
-                            at 16. Changes the grouping of the FP32 gradient sums, not the
+                            (16), or 8 or 16. For Euler-Maruyama ensembles of at least two
+                            wavefronts per SIMD the backward runs two wavefronts per SIMD at
+                            either length (16 is faster, with K <= 64 its sub-checkpoints stay in
+                            LDS); the Heun backward runs one wavefront per SIMD either way and is
+                            faster at 16. Changes the grouping of the FP32 gradient sums, not the
                             recursion */
 } abp_adjoint_cfg;
 

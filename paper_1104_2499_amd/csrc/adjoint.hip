@@ -566,8 +566,13 @@ __device__ __forceinline__ void flush(Rev &r, double (&A64)[kSums])
 // SUBL (with ZLDS): the segment's sub-checkpoints are kept in LDS too, after the noise, so that
 // reading the next one costs an LDS read rather than an L2 round trip (the compiler parks the
 // prefetched values in accumulation registers, which waits for them).
-template <int SCHEME, int VFORM, bool ZLDS, int NB, bool SUBL>
-__global__ __launch_bounds__(256) void k_adj_backward(AdjArgs a, const AdjRow *__restrict__ rows)
+//
+// OCC: wavefronts per SIMD the kernel is built for (2: at most 256 registers, for ensembles with
+// at least two wavefronts per SIMD; 1: the registers the schedule wants, for the one-wavefront
+// case).
+template <int SCHEME, int VFORM, bool ZLDS, int NB, bool SUBL, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_adj_backward(AdjArgs a,
+                                                           const AdjRow *__restrict__ rows)
 {
     using ST = Stage<SCHEME, NB>;
     constexpr int kStage = NB;
@@ -829,6 +834,27 @@ static bool layout_fits(int32_t n_sets, int64_t n, int64_t S, int64_t K)
     return lanes * slots * 28u < ((unsigned __int128)1 << 62);
 }
 
+// Launch one backward variant: the LDS forms the host chose (ZLDS, and SUBL for 16-step staging).
+template <int SCHEME, int VFORM, int NB, int OCC>
+static void launch_backward(bool zlds, bool subl, unsigned grid, size_t lds, hipStream_t st,
+                            const AdjArgs &a)
+{
+    const dim3 g(grid), b(256);
+    if constexpr (NB == 16) {
+        if (subl) {
+            hipLaunchKernelGGL((k_adj_backward<SCHEME, VFORM, true, NB, true, OCC>), g, b, lds, st,
+                               a, a.rows);
+            return;
+        }
+    }
+    if (zlds)
+        hipLaunchKernelGGL((k_adj_backward<SCHEME, VFORM, true, NB, false, OCC>), g, b, lds, st, a,
+                           a.rows);
+    else
+        hipLaunchKernelGGL((k_adj_backward<SCHEME, VFORM, false, NB, false, OCC>), g, b, 0, st, a,
+                           a.rows);
+}
+
 extern "C" size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set, int64_t n_steps,
                                               int64_t ckpt_every)
 {
@@ -970,16 +996,19 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         else
             hipLaunchKernelGGL((k_adj_forward<0, 1>), dim3(grid), dim3(256), 0, st, a, a.rows);
     } else {
-        // B = 16 is the default for both schemes: one wavefront per SIMD. B = 8 (on request) fits
-        // two Euler-Maruyama wavefronts per SIMD; the Heun backward runs one wavefront per SIMD at
-        // either staging length.
+        // B = 16 is the default for both schemes. Euler-Maruyama runs two wavefronts per SIMD when
+        // the ensemble has at least two per SIMD: with 16-step staging through the kernel built for
+        // 256 registers, with 8-step staging (on request) at its natural size. The Heun backward
+        // runs one wavefront per SIMD at either staging length.
         const int B = cfg->stage_steps == 8 ? 8 : 16;
-        const int blocks_per_cu = (!heun && B == 8) ? 2 : 1;
+        const int cus = device_cus();
+        const bool two = !heun && cus > 0 && waves >= (int64_t)cus * 4 * 2;
+        const int blocks_per_cu = (!heun && (B == 8 || two)) ? 2 : 1;
         // level-1 noise in LDS when every resident block's copy fits (and one block's share is
         // allowed); else it is regenerated
         a.z_slots = (int32_t)(heun ? a.K : a.K - B);
-        // per 256-thread block (4 wavefronts): the noise, and with 16-step staging (one block per
-        // CU) the sub-checkpoints of one segment (all but its last sub-window)
+        // per 256-thread block (4 wavefronts): the noise, and with 16-step staging the
+        // sub-checkpoints of one segment (all but its last sub-window)
         const auto fits = [&](size_t bytes) {
             return bytes * blocks_per_cu <= lds_per_cu_limit() && bytes <= lds_per_block_limit();
         };
@@ -989,57 +1018,22 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         const bool subl = zlds && B == 16 && fits(4 * sizeof(float) * (z_floats + sub_floats));
         a.lds_wave = (int32_t)(z_floats + (subl ? sub_floats : 0));
         const size_t lds = zlds ? 4 * sizeof(float) * (size_t)a.lds_wave : 0;
-        const dim3 g3(grid), b3(256);
-        if (heun && B == 16) {
-            if (subl)
-                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 16, true>), g3, b3, lds, st, a,
-                                   a.rows);
-            else if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 16, false>), g3, b3, lds, st, a,
-                                   a.rows);
-            else
-                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 16, false>), g3, b3, 0, st, a,
-                                   a.rows);
-        } else if (heun) {
-            if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<1, 0, true, 8, false>), g3, b3, lds, st, a,
-                                   a.rows);
-            else
-                hipLaunchKernelGGL((k_adj_backward<1, 0, false, 8, false>), g3, b3, 0, st, a,
-                                   a.rows);
-        } else if (B == 8) {
-            if (a.vform && zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 8, false>), g3, b3, lds, st, a,
-                                   a.rows);
-            else if (a.vform)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 8, false>), g3, b3, 0, st, a,
-                                   a.rows);
-            else if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 8, false>), g3, b3, lds, st, a,
-                                   a.rows);
-            else
-                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 8, false>), g3, b3, 0, st, a,
-                                   a.rows);
-        } else {
-            if (a.vform && subl)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 16, true>), g3, b3, lds, st, a,
-                                   a.rows);
-            else if (a.vform && zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, true, 16, false>), g3, b3, lds, st, a,
-                                   a.rows);
-            else if (a.vform)
-                hipLaunchKernelGGL((k_adj_backward<0, 1, false, 16, false>), g3, b3, 0, st, a,
-                                   a.rows);
-            else if (subl)
-                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 16, true>), g3, b3, lds, st, a,
-                                   a.rows);
-            else if (zlds)
-                hipLaunchKernelGGL((k_adj_backward<0, 0, true, 16, false>), g3, b3, lds, st, a,
-                                   a.rows);
-            else
-                hipLaunchKernelGGL((k_adj_backward<0, 0, false, 16, false>), g3, b3, 0, st, a,
-                                   a.rows);
-        }
+        if (heun && B == 16)
+            launch_backward<1, 0, 16, 1>(zlds, subl, grid, lds, st, a);
+        else if (heun)
+            launch_backward<1, 0, 8, 1>(zlds, subl, grid, lds, st, a);
+        else if (B == 8 && a.vform)
+            launch_backward<0, 1, 8, 1>(zlds, subl, grid, lds, st, a);
+        else if (B == 8)
+            launch_backward<0, 0, 8, 1>(zlds, subl, grid, lds, st, a);
+        else if (two && a.vform)
+            launch_backward<0, 1, 16, 2>(zlds, subl, grid, lds, st, a);
+        else if (two)
+            launch_backward<0, 0, 16, 2>(zlds, subl, grid, lds, st, a);
+        else if (a.vform)
+            launch_backward<0, 1, 16, 1>(zlds, subl, grid, lds, st, a);
+        else
+            launch_backward<0, 0, 16, 1>(zlds, subl, grid, lds, st, a);
     }
     if (hipGetLastError() != hipSuccess)
         return ABP_E_HIP;

@@ -30,7 +30,7 @@ WORKLOADS = {
     "adjoint-64k": dict(n=65536, steps=10_000, dt=1e-3, window=2_000, ckpt=100, seed=42),
     # batched adjoint driving Adam on (U0, a, d2)
     "adjoint-batched-1k": dict(n_sets=1024, n=1024, steps=50_000, dt=1e-3, window=10_000,
-                               ckpt=80, stage=8, iters=50, seed=3),
+                               ckpt=48, stage=16, iters=50, seed=3),
 }
 
 

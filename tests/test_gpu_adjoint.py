@@ -351,8 +351,8 @@ def test_eight_step_staging(gpu, orc):
 
 def test_batched_workload_full_size_sampled(gpu, orc):
     """The batched-adjoint workload at full size, in the launch configuration the benchmark times:
-    1024 sets x 1024 particles x 5e4 EM steps, W = 1e4, K = 80, 8-step staging (an 18.6 GB
-    workspace). Checked: the losses of sampled sets equal
+    1024 sets x 1024 particles x 5e4 EM steps, W = 1e4, K = 48, 16-step staging (a 31 GB
+    workspace; the backward kernel built for two wavefronts per SIMD). Checked: the losses of sampled sets equal
     the plain forward run of the same set bit for bit; every gradient is finite; each set's
     gradient is the mean of its per-particle gradients; and on the lowest-noise set and on set 0
     (256 sampled particles each), per-particle gradients of the particles whose FP64 gradient
