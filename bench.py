@@ -539,7 +539,7 @@ def main() -> int:
         return 0
 
     if args.adjoint_batched:
-        for stage, ckpt in ((16, 160), (8, 80), (8, 160), (16, 80)):
+        for stage, ckpt in ((16, 48), (16, 64), (16, 80), (16, 160), (8, 48), (8, 80), (8, 160)):
             print(json.dumps(adjoint_batched_bench(stage, ckpt)), flush=True)
         return 0
 
