@@ -17,7 +17,9 @@ import torch
 
 from . import api
 from .adjoint import GRAD_KEYS, AdjointConfig, mean_velocity, param_rows
-from .workloads import PARAM_KEYS, sweep_table
+from .workloads import PARAM_KEYS, WORKLOADS, sweep_table
+
+_WL = WORKLOADS["adjoint-batched-1k"]
 
 FREE = ("U0", "a", "d2")
 BOUNDS = {"U0": (0.05, 4.0), "a": (0.0, 0.5), "d2": (0.0, 2.0)}
@@ -41,8 +43,8 @@ def initial_theta(n_sets: int, seed: int) -> np.ndarray:
 
 
 def adam_ratchet(n_sets: int = 1024, n: int = 1024, steps: int = 50_000, window: int = 10_000,
-                 ckpt: int = 80, iters: int = 50, seed: int = 3, lr: float = 1e-2,
-                 lookback: int = 0, stage: int = 8, verbose: bool = False) -> AdamResult:
+                 ckpt: int = _WL["ckpt"], iters: int = 50, seed: int = 3, lr: float = 1e-2,
+                 lookback: int = 0, stage: int = _WL["stage"], verbose: bool = False) -> AdamResult:
     """Adam on (U0, a, d2) of n_sets sets maximising |L_k|. lookback > 0 uses the decayed adjoint
     estimator; the default is the exact pathwise gradient. The parameters live on the device for
     the whole loop (the library reads its parameter rows there)."""
@@ -96,8 +98,8 @@ if __name__ == "__main__":
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--steps", type=int, default=50_000)
     ap.add_argument("--window", type=int, default=10_000)
-    ap.add_argument("--ckpt", type=int, default=80)
-    ap.add_argument("--stage", type=int, default=8, choices=[0, 8, 16])
+    ap.add_argument("--ckpt", type=int, default=_WL["ckpt"])
+    ap.add_argument("--stage", type=int, default=_WL["stage"], choices=[0, 8, 16])
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--lookback", type=int, default=0)
