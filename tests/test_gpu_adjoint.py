@@ -349,6 +349,37 @@ def test_eight_step_staging(gpu, orc):
             adjoint.forward(adjoint.param_rows(_theta(1), cfg), cfg, adjoint.workspace(1, cfg))
 
 
+def test_two_wavefront_backward_matches_one_wavefront(gpu):
+    """Euler-Maruyama ensembles of at least two wavefronts per SIMD run the 16-step backward kernel
+    built for two wavefronts per SIMD. 160 sets x 1024 particles (2560 wavefronts) select it; set 0
+    alone (16 wavefronts) runs the one-wavefront kernel on the same particles and noise, and its
+    per-particle gradients must be the same bits. Checked with the segment's sub-checkpoints in LDS
+    (K = 48), with the noise only (K = 80) and with neither (K = 1203)."""
+    from paper_1104_2499_amd import adjoint
+
+    theta = _theta(160, jitter=0.2, seed=4)
+    n, S, W = 1024, 2000, 500
+    ref = None
+    for K in (48, 80, 1203):
+        cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=K, seed=9, stage=16)
+        ws = adjoint.workspace(160, cfg)
+        rows = adjoint.param_rows(theta, cfg)
+        adjoint.forward(rows, cfg, ws)
+        _, gp = adjoint.backward(rows, cfg, ws, torch.ones(160, dtype=torch.float64),
+                                 per_particle=True)
+        gp0 = gp[0].cpu().numpy()
+        del ws, gp
+        if ref is None:
+            ws1 = adjoint.workspace(1, cfg)
+            rows1 = adjoint.param_rows(theta[:1], cfg)
+            adjoint.forward(rows1, cfg, ws1)
+            _, ref = adjoint.backward(rows1, cfg, ws1, torch.ones(1, dtype=torch.float64),
+                                      per_particle=True)
+            ref = ref[0].cpu().numpy()
+        assert np.isfinite(gp0).all()
+        np.testing.assert_array_equal(gp0, ref, err_msg=f"K = {K}")
+
+
 def test_batched_workload_full_size_sampled(gpu, orc):
     """The batched-adjoint workload at full size, in the launch configuration the benchmark times:
     1024 sets x 1024 particles x 5e4 EM steps, W = 1e4, K = 48, 16-step staging (a 31 GB
