@@ -996,24 +996,25 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         else
             hipLaunchKernelGGL((k_adj_forward<0, 1>), dim3(grid), dim3(256), 0, st, a, a.rows);
     } else {
-        // B = 16 is the default for both schemes. Euler-Maruyama runs two wavefronts per SIMD when
-        // the ensemble has at least two per SIMD: with 16-step staging through the kernel built for
-        // 256 registers, with 8-step staging (on request) at its natural size. The Heun backward
-        // runs one wavefront per SIMD at either staging length.
+        // B = 16 is the default for both schemes. An Euler-Maruyama ensemble of at least two
+        // wavefronts per SIMD runs two blocks per CU (whether or not the noise then fits in LDS:
+        // the occupancy is worth more than the LDS copy): the 8-step kernel as it is, the 16-step
+        // one through its build for 256 registers. Smaller ensembles, and the Heun backward, run
+        // one wavefront per SIMD, with LDS sized for that one block.
         const int B = cfg->stage_steps == 8 ? 8 : 16;
         const int cus = device_cus();
         const bool two = !heun && cus > 0 && waves >= (int64_t)cus * 4 * 2;
-        const int blocks_per_cu = (!heun && (B == 8 || two)) ? 2 : 1;
-        // level-1 noise in LDS when every resident block's copy fits (and one block's share is
-        // allowed); else it is regenerated
+        const int blocks_per_cu = two ? 2 : 1;
         a.z_slots = (int32_t)(heun ? a.K : a.K - B);
         // per 256-thread block (4 wavefronts): the noise, and with 16-step staging the
         // sub-checkpoints of one segment (all but its last sub-window)
+        const size_t z_floats = (size_t)a.z_slots * 64;
+        const size_t sub_floats = (size_t)(a.K / B - 1) * 7 * 64;
+        // level-1 noise in LDS when every resident block's copy fits (and one block's share is
+        // allowed); else it is regenerated
         const auto fits = [&](size_t bytes) {
             return bytes * blocks_per_cu <= lds_per_cu_limit() && bytes <= lds_per_block_limit();
         };
-        const size_t z_floats = (size_t)a.z_slots * 64;
-        const size_t sub_floats = (size_t)(a.K / B - 1) * 7 * 64;
         const bool zlds = a.z_slots > 0 && fits(4 * sizeof(float) * z_floats);
         const bool subl = zlds && B == 16 && fits(4 * sizeof(float) * (z_floats + sub_floats));
         a.lds_wave = (int32_t)(z_floats + (subl ? sub_floats : 0));

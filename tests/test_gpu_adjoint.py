@@ -316,8 +316,9 @@ def test_degenerate_sizes(gpu, orc, scheme, n, S, W, K):
 
 
 def test_eight_step_staging(gpu, orc):
-    """stage = 8 (two wavefronts per SIMD): the same recursion with the FP32 gradient sums grouped
-    in 8-step windows. Bit-identical loss, K-independent gradient, within FP32 rounding of the
+    """stage = 8 (the kernel that fits two wavefronts per SIMD; this small ensemble runs one, with
+    the noise in LDS at K = 48 and 100 and regenerated at K = 1000): the same recursion with the
+    FP32 gradient sums grouped in 8-step windows. Bit-identical loss, K-independent gradient, within FP32 rounding of the
     16-step staging and within 1e-3 of the FP64 adjoint; invalid stagings are rejected."""
     from paper_1104_2499_amd import adjoint, api
 
