@@ -506,6 +506,61 @@ def adjoint_batched_item(iters: int = 50) -> dict:
                                                                             r.verify_mean_v))}}
 
 
+def adjoint_gradient_snr() -> list[dict]:
+    """How informative the per-set gradients of the batched-adjoint sets are (1024 sets x 1024
+    particles, EM, dt = 1e-3, the Adam loop's initial parameters, K = 48): for the exact pathwise
+    gradient at a short (1e4 steps, W = 2e3) and at the workload's horizon (5e4, W = 1e4), and the
+    decayed estimator (look-back 1000) at the latter, per set and per Adam parameter (U0, a, d2)
+    the |mean| of the per-particle gradients over its standard error, and their RMS; beside them
+    the objective's own |<v>| over its standard error from the plain batched forward. Medians
+    over the sets."""
+    import numpy as np
+    import torch
+
+    from paper_1104_2499_amd import adjoint, api
+    from paper_1104_2499_amd.optimize import initial_theta
+    from paper_1104_2499_amd.workloads import WORKLOADS
+
+    wl = WORKLOADS["adjoint-batched-1k"]
+    n_sets, n = wl["n_sets"], wl["n"]
+    theta = torch.tensor(initial_theta(n_sets, wl["seed"]))
+    cols = [adjoint.GRAD_KEYS.index(k) for k in ("U0", "a", "d2")]
+    out = []
+    for steps, window, lookback in ((10_000, 2_000, 0), (wl["steps"], wl["window"], 0),
+                                    (wl["steps"], wl["window"], 1000)):
+        cfg = adjoint.AdjointConfig(n=n, steps=steps, window=window, ckpt=wl["ckpt"],
+                                    seed=wl["seed"], lookback=lookback, stage=wl["stage"])
+        rows = adjoint.param_rows(theta, cfg)
+        buf = api.SweepBuffers.make(rows, np.full(n_sets, n, np.int32),
+                                    np.full(n_sets, steps, np.int64),
+                                    np.full(n_sets, window, np.int64), bins=0)
+        api.sweep_enqueue(buf, wl["dt"], "em", wl["seed"], 0)
+        torch.cuda.synchronize()
+        api.check_device_status(buf.status, "sweep")
+        mv = buf.out.cpu().numpy()
+        del buf
+        ws = adjoint.workspace(n_sets, cfg)
+        loss = adjoint.forward(rows, cfg, ws)
+        _, gp = adjoint.backward(rows, cfg, ws, torch.ones(n_sets, dtype=torch.float64),
+                                 per_particle=True)
+        g = gp[:, :, cols]
+        snr = (g.mean(1).abs() / (g.std(1) / n ** 0.5)).cpu().numpy()
+        rms = g.square().mean(1).sqrt().cpu().numpy()
+        del ws, gp, g
+        torch.cuda.empty_cache()
+        out.append({"workload": "adjoint-batched-1k", "steps": steps, "window": window,
+                    "estimator": "exact" if lookback == 0 else f"lookback {lookback}",
+                    "loss_equals_plain_forward": bool(np.array_equal(loss.cpu().numpy(),
+                                                                     mv[:, 0])),
+                    "objective_abs_over_stderr": float(np.median(np.abs(mv[:, 0]) / mv[:, 1])),
+                    "grad_abs_over_stderr": dict(zip(("U0", "a", "d2"),
+                                                     np.median(snr, 0).tolist())),
+                    "sets_with_grad_over_2_stderr": dict(zip(("U0", "a", "d2"),
+                                                             (snr > 2).mean(0).tolist())),
+                    "grad_rms": dict(zip(("U0", "a", "d2"), np.median(rms, 0).tolist()))})
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -528,6 +583,9 @@ def main() -> int:
                     help="checkpoint intervals for --adjoint-only (default: the workload's)")
     ap.add_argument("--adjoint-batched", action="store_true",
                     help="only one batched-adjoint iteration per (staging, K) variant")
+    ap.add_argument("--adjoint-snr", action="store_true",
+                    help="only the signal-to-noise of the batched-adjoint gradients, one JSON line "
+                         "per horizon and estimator")
     ap.add_argument("--cpu-baselines", action="store_true",
                     help="only the FP64 oracle on every workload (all host cores and one) beside "
                          "the GPU time of the same workload, one JSON line each")
@@ -541,6 +599,11 @@ def main() -> int:
     if args.adjoint_batched:
         for stage, ckpt in ((16, 48), (16, 64), (16, 80), (16, 160), (8, 48), (8, 80), (8, 160)):
             print(json.dumps(adjoint_batched_bench(stage, ckpt)), flush=True)
+        return 0
+
+    if args.adjoint_snr:
+        for r in adjoint_gradient_snr():
+            print(json.dumps(r), flush=True)
         return 0
 
     if args.adjoint_only:
