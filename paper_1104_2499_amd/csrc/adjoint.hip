@@ -9,18 +9,18 @@
 // Forward phase: each lane integrates its particle from the workload initial condition and stores
 // its whole state (28 bytes) every K steps. Backward phase: for each segment [jK, (j+1)K) in
 // reverse, the lane restores the checkpoint and recomputes the segment with regenerated Philox
-// noise, leaving sub-checkpoints at absolute multiples of B steps in workspace memory (B = 16 by
-// default, or 8: for Euler-Maruyama that lets two wavefronts share a SIMD; K is rounded up to a
-// multiple of 16). Then, for each sub-window in reverse, it restores the sub-checkpoint,
+// noise, leaving sub-checkpoints at absolute multiples of B steps (B = 16 by default, or 8; K is
+// rounded up to a multiple of 16) in the workspace, or in LDS beside the noise when both fit
+// (16-step staging). Then, for each sub-window in reverse, it restores the sub-checkpoint,
 // recomputes the sub-window while staging the values the reverse step needs (cos and sin of the
 // phase, v, e at every point where the drift is evaluated, and sigma*xi) in registers, and runs
 // the adjoint recursion backwards over it. When the segment's noise fits in LDS (at most K steps
-// x 64 lanes x 4 bytes per wavefront; one four-wavefront block per CU with 16-step staging, two
-// with 8-step staging), level 1 keeps each sigma*xi it draws there and the staged recomputation
-// reads it back instead of running Philox and Box-Muller a second time. Euler-Maruyama keeps the
-// K - B steps level 1 draws; Heun keeps the last sub-window's noise too (drawn by its staged
-// recomputation), K steps in all, and its reverse steps read sigma*xi there instead of from
-// registers. The recomputation reproduces the forward bits exactly (the integrator's state is
+// x 64 lanes x 4 bytes per wavefront, for every four-wavefront block resident on a CU: one, or
+// two for Euler-Maruyama ensembles of at least two wavefronts per SIMD), level 1 keeps each
+// sigma*xi it draws there and the staged recomputation reads it back instead of running Philox
+// and Box-Muller a second time. Euler-Maruyama keeps the K - B steps level 1 draws; Heun keeps
+// the last sub-window's noise too (drawn by its staged recomputation), K steps in all, and its
+// reverse steps read sigma*xi there instead of from registers. The recomputation reproduces the forward bits exactly (the integrator's state is
 // resumable mid-span), so the result does not depend on K. Per-step gradient terms are summed in
 // FP32 within each absolute B-step window and in FP64 across windows (that grouping does not
 // depend on K either); tiles of 64 particles and sets are then reduced in a fixed order.
@@ -216,9 +216,10 @@ __global__ __launch_bounds__(256) void k_adj_forward(AdjArgs a, const AdjRow *__
 // Values of one sub-window staged for the reverse sweep, per step: cos and sin of the phase
 // 2 pi (x + phi), v and e (the rounded sums the drift saw), sigma xi; for Heun also cos, sin, v and
 // e at the predictor point (the values the step's second drift saw).
-// NB = steps per sub-window, 16 or 8. For Euler-Maruyama 8 stages half the registers, so that two
-// wavefronts fit one SIMD; the Heun kernel holds one wavefront per SIMD either way, and 16 halves
-// the per-window overheads.
+// NB = steps per sub-window, 16 or 8. 16 halves the per-window overheads; for Euler-Maruyama 8
+// stages half the registers, so that two wavefronts fit one SIMD at the kernel's natural size
+// (the 16-step kernel has a build capped at 256 registers for that). The Heun kernel holds one
+// wavefront per SIMD either way.
 template <int SCHEME, int NB>
 struct Stage;
 
