@@ -543,10 +543,10 @@ def adjoint_gradient_snr() -> list[dict]:
         loss = adjoint.forward(rows, cfg, ws)
         _, gp = adjoint.backward(rows, cfg, ws, torch.ones(n_sets, dtype=torch.float64),
                                  per_particle=True)
-        g = gp[:, :, cols]
-        snr = (g.mean(1).abs() / (g.std(1) / n ** 0.5)).cpu().numpy()
-        rms = g.square().mean(1).sqrt().cpu().numpy()
-        del ws, gp, g
+        g = gp[:, :, cols].cpu().numpy()  # statistics on the host
+        snr = np.abs(g.mean(1)) / (g.std(1, ddof=1) / n ** 0.5)
+        rms = np.sqrt((g * g).mean(1))
+        del ws, gp
         torch.cuda.empty_cache()
         out.append({"workload": "adjoint-batched-1k", "steps": steps, "window": window,
                     "estimator": "exact" if lookback == 0 else f"lookback {lookback}",
