@@ -2,8 +2,9 @@
 // the HIP runtime's C API; no Python, no torch). It allocates the state, snapshot, reduction
 // workspace and outputs with hipMalloc, runs the initial condition, one integration call with the
 // window snapshot and fused reduction, and the finalize; then a three-set batched sweep whose
-// parameter, trajectory, step and window tables it copies into device memory. It prints one JSON
-// line with the results and the status of calls that must be rejected.
+// parameter, trajectory, step and window tables it copies into device memory; then the adjoint's
+// forward and backward phases for a two-set parameter table. It prints one JSON line with the
+// results and the status of calls that must be rejected.
 //
 // usage: abi_client n steps window scheme(0 = EM, 1 = Heun) seed
 #include <hip/hip_runtime_api.h>
@@ -157,14 +158,70 @@ int main(int argc, char **argv)
         abp_batched_workspace_bytes(n_sets, n_sets, bins) - 256, d_bout, d_bhist, d_bstatus,
         nullptr);
 
+    // adjoint over a device parameter table: the base ratchet and U0 = 1.5, 700 particles each,
+    // checkpoints every 100 steps; the backward phase weights the two losses by 1 and 1/2
+    const int32_t a_sets = 2;
+    const int64_t a_n = 700, a_ckpt = 100;
+    abp_params h_ap[a_sets] = {p, p};
+    h_ap[1].U0 = 1.5;
+    const double h_gloss[a_sets] = {1.0, 0.5};
+    abp_adjoint_cfg acfg = {};
+    acfg.dt = dt;
+    acfg.n_steps = steps;
+    acfg.window = window;
+    acfg.ckpt_every = a_ckpt;
+    acfg.seed = seed;
+    acfg.lookback = 0;
+    acfg.scheme = scheme;
+    acfg.stage_steps = 0;
+    const size_t aws_bytes = abp_adjoint_workspace_bytes(a_sets, a_n, steps, a_ckpt);
+    abp_params *d_ap = nullptr;
+    void *d_aws = nullptr;
+    double *d_loss = nullptr, *d_gloss = nullptr, *d_grad = nullptr;
+    int32_t *d_astatus = nullptr;
+    HIP_OK(hipMalloc((void **)&d_ap, sizeof h_ap));
+    HIP_OK(hipMalloc(&d_aws, aws_bytes));
+    HIP_OK(hipMalloc((void **)&d_loss, a_sets * sizeof(double)));
+    HIP_OK(hipMalloc((void **)&d_gloss, sizeof h_gloss));
+    HIP_OK(hipMalloc((void **)&d_grad, 8 * a_sets * sizeof(double)));
+    HIP_OK(hipMalloc((void **)&d_astatus, sizeof(int32_t)));
+    HIP_OK(hipMemcpy(d_ap, h_ap, sizeof h_ap, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(d_gloss, h_gloss, sizeof h_gloss, hipMemcpyHostToDevice));
+    ABP_OK_OR_EXIT(abp_adjoint(0, a_sets, d_ap, a_n, &acfg, d_aws, aws_bytes, d_loss, nullptr,
+                               nullptr, nullptr, d_astatus, nullptr));
+    ABP_OK_OR_EXIT(abp_adjoint(1, a_sets, d_ap, a_n, &acfg, d_aws, aws_bytes, nullptr, d_gloss,
+                               d_grad, nullptr, d_astatus, nullptr));
+    double loss[a_sets], grad[8 * a_sets];
+    int32_t astatus = -1;
+    HIP_OK(hipMemcpy(loss, d_loss, sizeof loss, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(grad, d_grad, sizeof grad, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&astatus, d_astatus, sizeof astatus, hipMemcpyDeviceToHost));
+    // a window longer than the run is rejected on the host
+    abp_adjoint_cfg bad_a = acfg;
+    bad_a.window = steps + 1;
+    const abp_status adj_rejected = abp_adjoint(0, a_sets, d_ap, a_n, &bad_a, d_aws, aws_bytes,
+                                                d_loss, nullptr, nullptr, nullptr, d_astatus,
+                                                nullptr);
+
     std::printf("{\"abi_version\": %d, \"mean_v\": %.17g, \"stderr\": %.17g, \"hist_total\": %llu, "
                 "\"hist_first\": %llu, \"rejected\": \"%s\", \"short_workspace\": \"%s\", "
                 "\"sweep_status\": %d, \"sweep_mean_v\": [%.17g, %.17g, %.17g], "
-                "\"sweep_stderr\": [%.17g, %.17g, %.17g], \"sweep_short_workspace\": \"%s\"}\n",
+                "\"sweep_stderr\": [%.17g, %.17g, %.17g], \"sweep_short_workspace\": \"%s\", "
+                "\"adjoint_status\": %d, \"adjoint_loss\": [%.17g, %.17g], \"adjoint_grad\": [",
                 abp_abi_version(), out[0], out[1], (unsigned long long)total,
                 (unsigned long long)hist[0], abp_status_str(rejected), abp_status_str(short_ws),
                 bstatus, bout[0], bout[2], bout[4], bout[1], bout[3], bout[5],
-                abp_status_str(short_bws));
+                abp_status_str(short_bws), astatus, loss[0], loss[1]);
+    for (int j = 0; j < 8 * a_sets; ++j)
+        std::printf("%s%.17g", j ? ", " : "", grad[j]);
+    std::printf("], \"adjoint_rejected\": \"%s\"}\n", abp_status_str(adj_rejected));
+
+    HIP_OK(hipFree(d_ap));
+    HIP_OK(hipFree(d_aws));
+    HIP_OK(hipFree(d_loss));
+    HIP_OK(hipFree(d_gloss));
+    HIP_OK(hipFree(d_grad));
+    HIP_OK(hipFree(d_astatus));
 
     HIP_OK(hipFree(d_params));
     HIP_OK(hipFree(d_ntraj));

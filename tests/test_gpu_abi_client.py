@@ -1,7 +1,8 @@
 """The C ABI from a plain host program (tests/c_client/abi_client.cpp: include/abp.h and the HIP
 runtime's C API, no Python binding, no torch): its results equal the Python binding's bit for bit
-and invalid calls are rejected with the documented statuses. The client runs as a child process,
-started before this process touches the GPU."""
+and invalid calls are rejected with the documented statuses: the single-set integrator and
+reduction, the batched sweep and the adjoint's two phases over device parameter tables. The client
+runs as a child process, started before this process touches the GPU."""
 import json
 import os
 import subprocess
@@ -46,3 +47,18 @@ def test_c_client_equals_python_binding(scheme):
         r = api.run(params, n=n_k, steps=s_k, window=w_k, scheme=scheme, seed=seed, bins=256,
                     set_id=k)
         assert got["sweep_mean_v"][k] == r.mean_v and got["sweep_stderr"][k] == r.stderr
+    # the adjoint over a device table: loss and weighted gradient equal the binding's bit for bit
+    from paper_1104_2499_amd import adjoint
+
+    assert got["adjoint_status"] == 0
+    assert got["adjoint_rejected"] == "invalid argument"
+    cfg = adjoint.AdjointConfig(n=700, steps=steps, window=window, ckpt=100, seed=seed,
+                                scheme=scheme)
+    theta = torch.tensor([[BASE_PARAMS[k] for k in adjoint.GRAD_KEYS]] * 2, dtype=torch.float64)
+    theta[1, adjoint.GRAD_KEYS.index("U0")] = 1.5
+    rows = adjoint.param_rows(theta, cfg)
+    ws = adjoint.workspace(2, cfg)
+    loss = adjoint.forward(rows, cfg, ws).cpu().numpy()
+    grad = adjoint.backward(rows, cfg, ws, torch.tensor([1.0, 0.5], dtype=torch.float64))
+    assert got["adjoint_loss"] == loss.tolist()
+    assert got["adjoint_grad"] == grad.cpu().numpy().reshape(-1).tolist()
