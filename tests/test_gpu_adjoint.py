@@ -130,10 +130,12 @@ def test_batched_adjoint_sets_match_oracle(gpu, orc):
                                    atol=1e-6 * np.abs(want).max())
 
 
-def test_full_horizon_per_particle_gradients(gpu, orc):
-    """G3 at the 65536-particle, 1e4-step, W = 2000, K = 100 configuration, on 8192 sampled
-    particles: (i) per particle and component, the GPU-oracle gradient difference is within twice
-    the oracle's own change under FP32-sized path perturbations (2^-24 model), for >= 99% of the
+@pytest.mark.parametrize("scheme", ["em", "heun"])
+def test_full_horizon_per_particle_gradients(gpu, orc, scheme):
+    """G3 at the 65536-particle, 1e4-step, W = 2000, K = 100 configuration (the Euler-Maruyama
+    workload, and the same shape through the stochastic Heun map), on 8192 sampled particles:
+    (i) per particle and component, the GPU-oracle gradient difference is within twice the
+    oracle's own change under FP32-sized path perturbations (2^-24 model), for >= 99% of the
     pairs; (ii) summed over the particles whose FP64 gradient is well-conditioned (every component
     changes by < 1e-4 relative under that perturbation; about 7% of the particles at this
     horizon), the GPU gradient matches within 1e-3 relative."""
@@ -141,18 +143,19 @@ def test_full_horizon_per_particle_gradients(gpu, orc):
 
     theta = _theta(1)
     n, S, W = 65536, 10_000, 2_000
-    cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=100, seed=42)
+    cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=100, seed=42, scheme=scheme)
     rows = adjoint.param_rows(theta, cfg)
     ws = adjoint.workspace(1, cfg)
     loss = adjoint.forward(rows, cfg, ws)
     g, gp = adjoint.backward(rows, cfg, ws, torch.ones(1, dtype=torch.float64), per_particle=True)
-    run = api.run(_params(theta[0]), n=n, steps=S, window=W, scheme="em", seed=42, bins=0)
+    run = api.run(_params(theta[0]), n=n, steps=S, window=W, scheme=scheme, seed=42, bins=0)
     assert float(loss[0].cpu()) == run.mean_v
     ids = np.arange(0, n, 8, dtype=np.uint64)  # 8192 sampled particles
     x0, v0, e0 = orc.init_state(ids.size, 42, ids=ids)
     p = _params(theta[0])
-    _, g_ora = orc.adjoint(p, x0, v0, e0, S, W, seed=42, ids=ids)
-    _, g_eps = orc.adjoint(p, x0, v0, e0, S, W, seed=42, ids=ids, eps=2.0**-24)
+    sid = 0 if scheme == "em" else 1
+    _, g_ora = orc.adjoint(p, x0, v0, e0, S, W, seed=42, ids=ids, scheme=sid)
+    _, g_eps = orc.adjoint(p, x0, v0, e0, S, W, seed=42, ids=ids, eps=2.0**-24, scheme=sid)
     gpp = gp[0].cpu().numpy()[ids.astype(np.int64)]
     scale = np.abs(g_ora).max(axis=0)
     d_gpu = np.abs(gpp - g_ora)
@@ -160,7 +163,8 @@ def test_full_horizon_per_particle_gradients(gpu, orc):
     within = d_gpu <= 2 * d_own + 1e-6 * scale
     floor = np.maximum(np.abs(g_ora), 1e-6 * scale)
     C = (d_own / floor < 1e-4).all(axis=1)
-    print(f"pairs within 2x own sensitivity: {within.mean():.4f}; well-conditioned particles "
+    print(f"{scheme}: pairs within 2x own sensitivity: {within.mean():.4f}; well-conditioned "
+          f"particles "
           f"{C.mean():.3f}; median |gpu-ora|/|ora| {np.median(d_gpu / floor):.2e}, "
           f"median own {np.median(d_own / floor):.2e}")
     assert within.mean() >= 0.99
@@ -318,8 +322,9 @@ def test_degenerate_sizes(gpu, orc, scheme, n, S, W, K):
 def test_eight_step_staging(gpu, orc):
     """stage = 8 (the kernel that fits two wavefronts per SIMD; this small ensemble runs one, with
     the noise in LDS at K = 48 and 100 and regenerated at K = 1000): the same recursion with the
-    FP32 gradient sums grouped in 8-step windows. Bit-identical loss, K-independent gradient, within FP32 rounding of the
-    16-step staging and within 1e-3 of the FP64 adjoint; invalid stagings are rejected."""
+    FP32 gradient sums grouped in 8-step windows. Bit-identical loss, K-independent gradient,
+    within FP32 rounding of the 16-step staging and within 1e-3 of the FP64 adjoint; invalid
+    stagings are rejected."""
     from paper_1104_2499_amd import adjoint, api
 
     n_sets, n, S, W = 3, 700, 1000, 200
@@ -384,9 +389,10 @@ def test_two_wavefront_backward_matches_one_wavefront(gpu):
 def test_batched_workload_full_size_sampled(gpu, orc):
     """The batched-adjoint workload at full size, in the launch configuration the benchmark times:
     1024 sets x 1024 particles x 5e4 EM steps, W = 1e4, K = 48, 16-step staging (a 31 GB
-    workspace; the backward kernel built for two wavefronts per SIMD). Checked: the losses of sampled sets equal
-    the plain forward run of the same set bit for bit; every gradient is finite; each set's
-    gradient is the mean of its per-particle gradients; and on the lowest-noise set and on set 0
+    workspace; the backward kernel built for two wavefronts per SIMD). Checked: the losses of
+    sampled sets equal the plain forward run of the same set bit for bit; every gradient is finite;
+    each set's gradient is the mean of its per-particle gradients; and on the lowest-noise set and
+    on set 0
     (256 sampled particles each), per-particle gradients of the particles whose FP64 gradient
     moves by < 1e-3 relative under FP32-sized path perturbations (2^-24 model) agree with the FP64
     adjoint within twice that movement plus 1e-3 relative (the gradient tolerance, applied per
