@@ -392,9 +392,8 @@ def test_batched_workload_full_size_sampled(gpu, orc):
     workspace; the backward kernel built for two wavefronts per SIMD). Checked: the losses of
     sampled sets equal the plain forward run of the same set bit for bit; every gradient is finite;
     each set's gradient is the mean of its per-particle gradients; and on the lowest-noise set and
-    on set 0
-    (256 sampled particles each), per-particle gradients of the particles whose FP64 gradient
-    moves by < 1e-3 relative under FP32-sized path perturbations (2^-24 model) agree with the FP64
+    on set 0 (256 sampled particles each), per-particle gradients of the particles whose FP64
+    gradient moves by < 1e-3 relative under FP32-sized path perturbations (2^-24 model) agree with the FP64
     adjoint within twice that movement plus 1e-3 relative (the gradient tolerance, applied per
     particle: over 5e4 reverse steps the FP32 recursion's own rounding reaches ~1e-4 to 1e-3
     relative, more than the FP64 gradient moves for some components). At this horizon most
