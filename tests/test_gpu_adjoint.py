@@ -355,19 +355,24 @@ def test_eight_step_staging(gpu, orc):
             adjoint.forward(adjoint.param_rows(_theta(1), cfg), cfg, adjoint.workspace(1, cfg))
 
 
-def test_two_wavefront_backward_matches_one_wavefront(gpu):
-    """Euler-Maruyama ensembles of at least two wavefronts per SIMD run the 16-step backward kernel
-    built for two wavefronts per SIMD. 160 sets x 1024 particles (2560 wavefronts) select it; set 0
-    alone (16 wavefronts) runs the one-wavefront kernel on the same particles and noise, and its
-    per-particle gradients must be the same bits. Checked with the segment's sub-checkpoints in LDS
-    (K = 48), with the noise only (K = 80) and with neither (K = 1203)."""
+@pytest.mark.parametrize("stage,ks", [(16, (48, 80, 1203)), (8, (48, 100, 1203))])
+def test_two_wavefront_backward_matches_one_wavefront(gpu, stage, ks):
+    """Euler-Maruyama ensembles of at least two wavefronts per SIMD run two backward blocks per
+    CU: the 16-step kernel through its build for two wavefronts per SIMD, the 8-step kernel as it
+    is, each with LDS sized for two blocks. 160 sets x 1024 particles (2560 wavefronts) select
+    that; set 0 alone (16 wavefronts) runs one wavefront per SIMD with LDS sized for one block, on
+    the same particles and noise, and its per-particle gradients must be the same bits. 16-step:
+    the segment's sub-checkpoints in LDS (K = 48), the noise only (K = 80), neither (K = 1203).
+    8-step: the noise in LDS at both sizings (K = 48), only for the lone set (K = 100), neither
+    (K = 1203)."""
     from paper_1104_2499_amd import adjoint
 
     theta = _theta(160, jitter=0.2, seed=4)
     n, S, W = 1024, 2000, 500
     ref = None
-    for K in (48, 80, 1203):
-        cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=K, seed=9, stage=16)
+    for K in ks:
+        print(f"stage {stage}, K = {K}", flush=True)
+        cfg = adjoint.AdjointConfig(n=n, steps=S, window=W, ckpt=K, seed=9, stage=stage)
         ws = adjoint.workspace(160, cfg)
         rows = adjoint.param_rows(theta, cfg)
         adjoint.forward(rows, cfg, ws)
