@@ -3,7 +3,6 @@ state, snapshot, mean velocity, standard error and histogram, bit for bit, on tw
 (the second on a smaller ensemble, so that stale scratch contents from the first would show)."""
 import ctypes
 
-import numpy as np
 import pytest
 import torch
 
