@@ -127,6 +127,8 @@ if __name__ == "__main__":
                                              "experiments")
     ap.add_argument("what", choices=["force", "scaling", "density"])
     ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--scheme", choices=["em", "heun"], default="em",
+                    help="integration scheme of the scaling measurement")
     args = ap.parse_args()
     if args.what == "force":
         F0 = np.linspace(-1.0, 0.5, 31)
@@ -145,6 +147,6 @@ if __name__ == "__main__":
         sizes = [2 ** k for k in range(0, 21)]
         if not args.quick:
             sizes += list(range(16384, 16384 * 40 + 1, 16384))
-        for row in scaling(sorted(set(sizes)), repeats=8 if args.quick else 20,
+        for row in scaling(sorted(set(sizes)), scheme=args.scheme, repeats=8 if args.quick else 20,
                            keep=5 if args.quick else 15):
             print(json.dumps(row), flush=True)
