@@ -468,8 +468,10 @@ def adjoint_batched_bench(stage: int, ckpt: int, reps: int = 3) -> dict:
 
 def adjoint_batched_item(iters: int = 50) -> dict:
     """The batched-adjoint workload (1024 sets x 1024 particles x 5e4 EM steps, W = 1e4; K = 48,
-    16-step staging, two wavefronts per SIMD): one forward + backward iteration against the plain batched forward of the
-    same sets, then the 50-iteration Adam loop on (U0, a, d2) with the exact pathwise gradient."""
+    16-step staging, two wavefronts per SIMD): one forward + backward iteration against the plain
+    batched forward of the same sets, then the 50-iteration Adam loop on (U0, a, d2) with the exact
+    pathwise gradient (the headline item), and beside it the same loop on the decayed estimator
+    (look-back 1000 steps)."""
     import numpy as np
     import torch
 
@@ -491,19 +493,22 @@ def adjoint_batched_item(iters: int = 50) -> dict:
     plain_ms = _gpu_ms(plain, 2)
     api.check_device_status(buf.status, "sweep")
     del buf
-    r = optimize.adam_ratchet(wl["n_sets"], wl["n"], wl["steps"], wl["window"], wl["ckpt"],
-                              iters, wl["seed"], stage=wl["stage"])
-    torch.cuda.empty_cache()
+    def adam(lookback: int, estimator: str) -> dict:
+        r = optimize.adam_ratchet(wl["n_sets"], wl["n"], wl["steps"], wl["window"], wl["ckpt"],
+                                  iters, wl["seed"], lookback=lookback, stage=wl["stage"])
+        torch.cuda.empty_cache()
+        return {"iterations": iters, "estimator": estimator, "seconds": r.seconds,
+                "mean_abs_v_start": float(r.history[0]), "mean_abs_v_end": float(r.history[-1]),
+                "mean_abs_v_rose": bool(r.history[-1] > r.history[0]),
+                "final_loss_equals_plain_forward": bool(np.array_equal(r.final_loss,
+                                                                       r.verify_mean_v))}
+    exact = adam(0, "exact pathwise gradient")
+    decayed = adam(1000, "decayed adjoint, look-back 1000 steps")
     return {"workload": "adjoint-batched-1k", "scheme": "em", "ckpt": wl["ckpt"],
             "stage": wl["stage"], "forward_ms": it["forward_ms"], "backward_ms": it["backward_ms"],
             "plain_forward_ms": plain_ms,
             "cost_ratio": (it["forward_ms"] + it["backward_ms"]) / plain_ms,
-            "adam": {"iterations": iters, "estimator": "exact pathwise gradient",
-                     "seconds": r.seconds, "mean_abs_v_start": float(r.history[0]),
-                     "mean_abs_v_end": float(r.history[-1]),
-                     "mean_abs_v_rose": bool(r.history[-1] > r.history[0]),
-                     "final_loss_equals_plain_forward": bool(np.array_equal(r.final_loss,
-                                                                            r.verify_mean_v))}}
+            "adam": exact, "adam_decayed": decayed}
 
 
 def adjoint_gradient_snr() -> list[dict]:
