@@ -121,7 +121,9 @@ typedef struct abp_tuning {
 } abp_tuning;
 
 int abp_abi_version(void);
-const char *abp_status_str(abp_status s);
+/* A static description of a status code; any int32 value is accepted ("unknown status" for
+ * values that are no abp_status). */
+const char *abp_status_str(int32_t status);
 
 /* Initial condition of an ensemble: the state (x, v, e) of Eqs. (1)-(2) at t = 0 for every work
  * item of Fig. 1 (the paper does not fix it, Sec. 2; here x0 ~ U[0,1) on the 24-bit grid,

@@ -63,7 +63,7 @@ _vp, _i32, _i64, _u32, _u64, _f64, _sz = (ctypes.c_void_p, ctypes.c_int32, ctype
 # name -> (restype, argtypes); mirrors include/abp.h
 SIGNATURES = {
     "abp_abi_version": (ctypes.c_int, []),
-    "abp_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "abp_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
     "abp_init_state": (ctypes.c_int, [_P(AbpState), _u64, _u32, _vp]),
     "abp_philox": (ctypes.c_int, [_i64, _vp, _vp, _vp, _vp]),
     "abp_reduce_workspace_bytes": (_sz, [_i64, _i32]),

@@ -91,9 +91,11 @@ using namespace abp;
 
 extern "C" int abp_abi_version(void) { return ABP_ABI_VERSION; }
 
-extern "C" const char *abp_status_str(abp_status s)
+extern "C" const char *abp_status_str(int32_t status)
 {
-    switch (s) {
+    // compared as an integer: a caller may pass any value, which an enum parameter of C++ could not
+    // hold without undefined behaviour
+    switch (status) {
     case ABP_OK: return "ok";
     case ABP_E_ARG: return "invalid argument";
     case ABP_E_HIP: return "HIP runtime error";
