@@ -860,7 +860,7 @@ extern "C" size_t abp_adjoint_workspace_bytes(int32_t n_sets, int64_t n_per_set,
                                               int64_t ckpt_every)
 {
     if (n_sets < 1 || n_per_set < 1 || n_steps < 1 || ckpt_every < 1 ||
-        (int64_t)n_sets * n_per_set > kMaxParticles || n_steps > kMaxStepIndex ||
+        n_per_set > kMaxParticles / n_sets || n_steps > kMaxStepIndex ||
         !layout_fits(n_sets, n_per_set, n_steps, ckpt_every))
         return 0;
     return adj_layout(n_sets, n_per_set, n_steps, ckpt_every).total;
@@ -921,7 +921,7 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
                                   void *stream)
 {
     if ((phase != 0 && phase != 1) || !d_params || !aligned(d_params, 8) || !cfg || n_sets < 1 ||
-        n_per_set < 1 || (int64_t)n_sets * n_per_set > kMaxParticles ||
+        n_per_set < 1 || n_per_set > kMaxParticles / n_sets ||
         n_per_set > 0xFFFFFFFFll || !aligned(d_status, 4))
         return ABP_E_ARG;
     if (!(cfg->dt > 0.0) || !is_finite(cfg->dt) || cfg->n_steps < 1 ||

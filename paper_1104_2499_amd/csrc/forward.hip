@@ -93,7 +93,7 @@ static abp_status plan_integrate(const abp_params *p, const abp_run *r, const ab
         return ABP_E_ARG;
     if (!(r->dt > 0.0) || !is_finite(r->dt) || !coef_ok(make_coef(*p, r->dt)) || r->n_steps < 0 ||
         r->step0 < 0 ||
-        r->n_steps > kMaxStepIndex || r->step0 + r->n_steps > kMaxStepIndex || r->win_begin < -1 ||
+        r->n_steps > kMaxStepIndex || r->step0 > kMaxStepIndex - r->n_steps || r->win_begin < -1 ||
         (r->scheme != ABP_EM && r->scheme != ABP_HEUN) || r->hist_stride < 0)
         return ABP_E_ARG;
     if (r->hist_stride > 0 && (r->hist_bins < 1 || !bins_ok(r->hist_bins) || !r->d_hist_acc ||
