@@ -1,6 +1,7 @@
 // adjoint.hip -- the adjoint's host code (abp_adjoint, abp_adjoint_workspace_bytes), the
 // per-set constants, the finalize kernel, and the kernel instances other than the 16-step
-// Euler-Maruyama backward of the exact gradient (the method is described in adjoint.hpp).
+// Euler-Maruyama backward of the exact gradient and the forward phase's look-ahead loop (the
+// method is described in adjoint.hpp).
 #include "adjoint.hpp"
 
 namespace abp {
@@ -223,12 +224,10 @@ extern "C" abp_status abp_adjoint(int32_t phase, int32_t n_sets, const abp_param
         // wavefronts per SIMD (its own instruction stream is all a SIMD has), else in place
         const int cus = device_cus();
         const bool ahead = cus > 0 && waves <= (int64_t)cus * 4 * 2;
-        if (heun && ahead)
-            hipLaunchKernelGGL((k_adj_forward<1, kAhead>), dim3(grid), dim3(256), 0, st, a, a.rows);
+        if (ahead)
+            launch_forward_ahead(heun, grid, st, a);
         else if (heun)
             hipLaunchKernelGGL((k_adj_forward<1, 1>), dim3(grid), dim3(256), 0, st, a, a.rows);
-        else if (ahead)
-            hipLaunchKernelGGL((k_adj_forward<0, kAhead>), dim3(grid), dim3(256), 0, st, a, a.rows);
         else
             hipLaunchKernelGGL((k_adj_forward<0, 1>), dim3(grid), dim3(256), 0, st, a, a.rows);
     } else {

@@ -37,8 +37,9 @@
 // (N = n_sets * tiles * 64 checkpoint slots: one per lane, also past a set's last particle)
 //
 // This header holds the kernels; adjoint_em.hip instantiates the 16-step Euler-Maruyama backward
-// of the exact gradient, adjoint.hip every other kernel and the host code (each source is built
-// with the instruction schedule that measured faster for its kernels).
+// of the exact gradient, adjoint_fwd.hip the forward phase's look-ahead loop, adjoint.hip every
+// other kernel and the host code (each source is built with the instruction schedule that
+// measured faster for its kernels).
 #pragma once
 
 #include "reduce.hpp"
@@ -782,6 +783,10 @@ inline void launch_backward(bool zlds, bool subl, unsigned grid, size_t lds, hip
         hipLaunchKernelGGL((k_adj_backward<SCHEME, VFORM, false, NB, false, OCC>), g, b, 0, st, a,
                            a.rows);
 }
+
+// The forward phase with the noise look-ahead loop (the small-ensemble form), defined in
+// adjoint_fwd.hip.
+void launch_forward_ahead(bool heun, unsigned grid, hipStream_t st, const AdjArgs &a);
 
 // The 16-step Euler-Maruyama backward launches for the exact gradient, defined in adjoint_em.hip:
 // wavefronts per SIMD occ (1, or 2 for the build capped at 256 registers).
